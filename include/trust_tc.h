@@ -1,0 +1,164 @@
+/*
+ * trust_tc.h -- exact triangle counting on MI355X (gfx950) by vertex-centric,
+ * hash-based list intersection on a degree-oriented CSR graph.
+ *
+ * Method: the vertex-centric hashing algorithm of the paper (Section 3,
+ * Algorithm 1): for every vertex u a hash table of its out-neighbour list is
+ * built once, then the out-neighbour list of every out-neighbour v of u is
+ * probed against it; each hit closes one triangle.  The graph is first cleaned
+ * (self-loops and duplicate edges dropped, pairs read as undirected; Section
+ * 2.6) and oriented by rank-by-degree (Section 2.2), ties broken by vertex id,
+ * so each triangle is found exactly once.  The result is the exact number of
+ * 3-cliques of the undirected simple graph (Sections 1 and 2.1) and,
+ * optionally, the number of triangles through each vertex.
+ *
+ * Conventions shared by every call:
+ *   - Memory: every device buffer is owned by the caller.  The library never
+ *     allocates or frees device memory; its scratch space comes from a
+ *     caller-provided workspace sized by the matching *_bytes query.  Host
+ *     memory is allocated only for the opaque handles.
+ *   - Ids: vertex ids are uint32 in [0, n), n <= 2^32 - 1.  Edge samples may
+ *     repeat, appear in both directions or be self-loops; all are accepted and
+ *     cleaned.  n = 0 or m_in = 0 gives a count of 0.
+ *   - Counts are uint64.  Per-vertex counts are indexed by input vertex id and
+ *     sum to 3 * total.
+ *   - Streams: `stream` is a hipStream_t (passed as void*); NULL means the
+ *     default stream.  All device work of a call is ordered on that stream.
+ *   - Errors: every call returns a tc_status and never aborts or throws across
+ *     the boundary.  tc_last_error() gives a message for the last failure on
+ *     a context.  After TC_E_DEVICE the context should be destroyed.
+ *   - Threads: a context may be used by one host thread at a time.
+ */
+#ifndef TRUST_TC_H
+#define TRUST_TC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TC_OK = 0,
+    TC_E_INVALID = 1,      /* null pointer where one is required, bad struct_size or parameter */
+    TC_E_RANGE = 2,        /* an input vertex id is >= n */
+    TC_E_NOMEM = 3,        /* workspace or storage smaller than the matching query returned */
+    TC_E_DEVICE = 4,       /* HIP error or no usable gfx950 device */
+    TC_E_UNSUPPORTED = 5,  /* size beyond the supported limits (m_in >= 2^31) */
+    TC_E_BUSY = 6          /* reserved for admission control by callers */
+} tc_status;
+
+/* Tuning knobs.  None of them changes any result, only speed; every
+ * combination accepted by tc_create / tc_set_params gives bit-identical counts. */
+typedef struct tc_params {
+    uint32_t struct_size;       /* = sizeof(tc_params) */
+    uint32_t wg_waves;          /* wavefronts per workgroup, 1..16 (workgroup = 64 * wg_waves lanes) */
+    uint32_t wg_lds_bytes;      /* LDS per workgroup for hash tables, 4096..131072 */
+    uint32_t wave_max_dplus;    /* out-degree at or below which one wavefront owns a vertex
+                                   (capped by what fits in wg_lds_bytes / wg_waves); 0 = largest that fits */
+    uint32_t slots_per_bucket;  /* S: 1, 2 or 4 slots per hash bucket */
+    uint32_t load_factor_pct;   /* buckets B = smallest power of two with B*S*load >= d+, and B >= d+; 10..100 */
+    uint32_t hash_kind;         /* 0: low bits of the degree rank; 1: multiplicative (Fibonacci) hash */
+    uint32_t light_chunk;       /* vertices a wavefront takes per queue access, 1..256 */
+    uint32_t grid_wgs;          /* persistent grid size in workgroups; 0 = fill the device */
+    uint32_t flags;             /* TC_F_* below */
+} tc_params;
+
+#define TC_F_NO_LPT     0x1u    /* keep rank order instead of largest-work-first within each bin */
+#define TC_F_FORCE_WG   0x2u    /* every vertex goes to the workgroup bin (tests) */
+#define TC_F_FORCE_HUB  0x4u    /* every vertex goes to the global-memory table path (tests) */
+#define TC_F_SORT_LISTS 0x8u    /* sort each out-neighbour list by rank after the CSR build */
+
+/* Opaque handles. */
+typedef struct tc_context tc_context;
+typedef struct tc_graph tc_graph;
+
+/* Summary of a built graph (all in the cleaned, oriented graph). */
+typedef struct tc_graph_info {
+    uint64_t n;           /* vertex count */
+    uint64_t m;           /* undirected edges after cleaning = oriented edges */
+    uint64_t wedges_plus; /* W+ = sum over oriented (u,v) of d+(v): the number of 2-hop probes */
+    uint32_t max_dplus;   /* largest out-degree */
+    uint32_t n_hub;       /* vertices in the global-memory table bin */
+    uint32_t n_wg;        /* vertices in the workgroup (LDS) bin */
+    uint32_t n_wave;      /* vertices in the wavefront (LDS) bin */
+    uint32_t wave_cap;    /* out-degree limits used for the bins */
+    uint32_t wg_cap;
+} tc_graph_info;
+
+/* Fill *p with the default knobs (struct_size set). */
+tc_status tc_default_params(tc_params* p);
+
+/* Create a context on HIP device `hip_device` (must be gfx950).  p may be NULL
+ * for the defaults; it is copied. */
+tc_status tc_create(int hip_device, const tc_params* p, tc_context** out);
+tc_status tc_destroy(tc_context* ctx);
+tc_status tc_set_params(tc_context* ctx, const tc_params* p);
+tc_status tc_get_params(const tc_context* ctx, tc_params* out);
+
+const char* tc_status_str(tc_status s);
+/* Message of the last failure on ctx ("" if none).  Valid until the next call on ctx. */
+const char* tc_last_error(const tc_context* ctx);
+
+/* ---------------------------------------------------------------- one-shot count
+ * Bytes of device workspace tc_count needs for a graph of n vertices and m_in
+ * input edge samples (an upper bound, independent of the edge values). */
+tc_status tc_workspace_bytes(const tc_context* ctx, uint32_t n, uint64_t m_in, uint64_t* bytes);
+
+/* Count the triangles of the undirected simple graph given by the samples
+ * (d_src[i], d_dst[i]), i < m_in (device arrays, read only, borrowed for the
+ * call).  d_per_vertex: NULL, or device uint64[n] overwritten with the number
+ * of triangles through each vertex.  d_ws: device workspace of ws_bytes >=
+ * tc_workspace_bytes(); its contents are clobbered.  Synchronises `stream`
+ * and writes the total to *h_total (host) on TC_OK. */
+tc_status tc_count(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d_src,
+                   const uint32_t* d_dst, uint64_t* d_per_vertex, void* d_ws, uint64_t ws_bytes,
+                   void* stream, uint64_t* h_total);
+
+/* ---------------------------------------------------------------- build once, count many
+ * tc_graph_footprint: device bytes a built graph keeps (storage) and the
+ * transient bytes its build needs (temp), for n vertices and m_in samples. */
+tc_status tc_graph_footprint(const tc_context* ctx, uint32_t n, uint64_t m_in,
+                             uint64_t* storage_bytes, uint64_t* temp_bytes);
+
+/* Clean, orient and lay out the graph in d_storage (caller-owned, must stay
+ * alive until tc_graph_release) and schedule its vertices into bins.  d_temp
+ * may be reused by the caller once the stream has passed this call.
+ * Asynchronous on `stream`; input range errors are reported by the next
+ * synchronous call on the graph (tc_graph_info_get). */
+tc_status tc_graph_build(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d_src,
+                         const uint32_t* d_dst, void* d_storage, uint64_t storage_bytes,
+                         void* d_temp, uint64_t temp_bytes, void* stream, tc_graph** out);
+
+/* Device scratch bytes one tc_graph_count call needs (per-vertex staging,
+ * queue heads, global-memory tables for the hub bin). */
+tc_status tc_count_scratch_bytes(const tc_context* ctx, uint32_t n, uint64_t m_in, uint64_t* bytes);
+
+/* Count the triangles of a built graph.  Asynchronous: the total is written
+ * to d_total (device uint64); d_per_vertex as in tc_count.  This call is one
+ * persistent kernel launch plus, with d_per_vertex, one gather launch. */
+tc_status tc_graph_count(tc_context* ctx, const tc_graph* g, uint64_t* d_total,
+                         uint64_t* d_per_vertex, void* d_scratch, uint64_t scratch_bytes,
+                         void* stream);
+
+/* Synchronise `stream` and read the graph's summary; returns TC_E_RANGE if
+ * the build saw an id >= n. */
+tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out);
+
+/* Free the handle (host memory only; the storage stays the caller's). */
+tc_status tc_graph_release(tc_graph* g);
+
+/* ---------------------------------------------------------------- timing
+ * With timing on, every tc_count / tc_graph_build / tc_graph_count records
+ * HIP events on its stream around its device steps (events owned by ctx).
+ * tc_timing_last waits for the last recorded events and returns, in
+ * milliseconds, the last build (clean, orient, CSR, bins) and the last count
+ * kernel launch alone; a value is -1 if that step has not run since timing
+ * was switched on. */
+tc_status tc_timing_enable(tc_context* ctx, int on);
+tc_status tc_timing_last(tc_context* ctx, float* build_ms, float* count_kernel_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRUST_TC_H */

@@ -1,0 +1,463 @@
+// C-ABI of the triangle-counting library: contexts, parameters, workspace
+// layout and the orchestration of the device steps.  See trust_tc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "tc_internal.h"
+
+struct tc_context {
+    int device = 0;
+    int cu_count = 0;
+    size_t lds_per_block_max = 0;
+    tc_params p{};
+    std::string err;
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // build start/end, count start/end
+    bool have_build = false, have_count = false;
+};
+
+struct tc_graph {
+    tc_context* ctx = nullptr;
+    uint32_t n = 0;
+    uint64_t m_in = 0;
+    tc_params p{};           // knobs the bins were sized with
+    tc::BinCaps caps{};
+    tc::GraphDev dev{};
+    bool empty = false;      // n == 0 or m_in == 0: nothing on the device
+};
+
+namespace {
+
+using tc::Layout;
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+tc_status fail(tc_context* c, tc_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+tc_status fail(tc_context* c, tc_status s, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+tc_status hip_fail(tc_context* c, hipError_t e, const char* where) {
+    return fail(c, TC_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                     \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+tc_status check_params(const tc_params* p) {
+    if (!p || p->struct_size != sizeof(tc_params)) return TC_E_INVALID;
+    if (p->wg_waves < 1 || p->wg_waves > tc::kMaxWaves) return TC_E_INVALID;
+    if (p->wg_lds_bytes < 4096 || p->wg_lds_bytes > 131072 || p->wg_lds_bytes % 16) return TC_E_INVALID;
+    if (p->slots_per_bucket != 1 && p->slots_per_bucket != 2 && p->slots_per_bucket != 4) return TC_E_INVALID;
+    if (p->load_factor_pct < 10 || p->load_factor_pct > 100) return TC_E_INVALID;
+    if (p->hash_kind > 1) return TC_E_INVALID;
+    if (p->light_chunk < 1 || p->light_chunk > 256) return TC_E_INVALID;
+    if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SORT_LISTS)) return TC_E_INVALID;
+    return TC_OK;
+}
+
+uint32_t slice_words(const tc_params& p) {
+    return (p.wg_lds_bytes / 4 / p.wg_waves) & ~3u;
+}
+
+tc::BinCaps bin_caps(const tc_params& p) {
+    tc::BinCaps c{};
+    // Capacities assume the per-vertex layout (the larger one), so one binning serves both modes.
+    c.wg_cap = tc::capacity(p.wg_lds_bytes / 4, p.slots_per_bucket, p.load_factor_pct, true);
+    c.wave_cap = tc::capacity(slice_words(p), p.slots_per_bucket, p.load_factor_pct, true);
+    if (p.wave_max_dplus && p.wave_max_dplus < c.wave_cap) c.wave_cap = p.wave_max_dplus;
+    c.force_wg = (p.flags & TC_F_FORCE_WG) != 0;
+    c.force_hub = (p.flags & TC_F_FORCE_HUB) != 0;
+    c.lpt = (p.flags & TC_F_NO_LPT) == 0;
+    c.sort_lists = (p.flags & TC_F_SORT_LISTS) != 0;
+    return c;
+}
+
+// Out-degree bound after (degree, id) orientation: every out-neighbour of u
+// has degree >= deg(u) >= d+(u), so d+(u)^2 <= 2m, and d+(u) < n.
+uint32_t dplus_bound(uint32_t n, uint64_t m_in) {
+    uint64_t b = (uint64_t)std::sqrt(2.0 * (double)m_in) + 2;
+    if (b > n) b = n;
+    if (b > m_in) b = m_in;
+    return (uint32_t)b;
+}
+
+Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_in) {
+    Layout L{};
+    size_t o = 0;
+    L.s_meta = o;  o = align_up(o + sizeof(tc::GraphMeta));
+    L.s_off = o;   o = align_up(o + sizeof(int64_t) * ((size_t)n + 1));
+    L.s_col = o;   o = align_up(o + sizeof(uint32_t) * (size_t)m_in);
+    L.s_rank = o;  o = align_up(o + sizeof(uint32_t) * (size_t)n);
+    L.s_items = o; o = align_up(o + sizeof(uint32_t) * (size_t)n);
+    L.storage = o;
+
+    o = 0;
+    L.t_keys_a = o; o = align_up(o + 8 * (size_t)m_in);
+    L.t_keys_b = o; o = align_up(o + 8 * (size_t)m_in);
+    L.t_deg = o;    o = align_up(o + 4 * ((size_t)n + 1));
+    L.t_dplus = o;  o = align_up(o + 4 * ((size_t)n + 1));
+    L.t_order = o;  o = align_up(o + 4 * (size_t)n);
+    L.t_skey_a = o; o = align_up(o + 8 * (size_t)n);
+    L.t_skey_b = o; o = align_up(o + 8 * (size_t)n);
+    L.sort_tmp_bytes = align_up(tc::prep_sort_tmp_bytes(n, m_in));
+    L.t_sort = o;   o = align_up(o + L.sort_tmp_bytes);
+    L.temp = o;
+
+    o = 0;
+    L.c_total = o;  o = align_up(o + 8);
+    L.c_heads = o;  o = align_up(o + 16);
+    L.c_tv = o;     o = align_up(o + 8 * (size_t)n);
+    const uint32_t dmax = dplus_bound(n, m_in);
+    L.hub_words = tc::geometry(dmax, p.slots_per_bucket, p.load_factor_pct, true).words;
+    uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)std::max(1, ctx ? ctx->cu_count : 1);
+    L.hub_wgs = std::min<uint32_t>(tc::kHubWgs, std::max<uint32_t>(1, grid));
+    L.c_hub = o;    o = align_up(o + 4 * L.hub_words * L.hub_wgs);
+    L.scratch = o;
+    return L;
+}
+
+tc::GraphDev graph_ptrs(void* storage, const Layout& L) {
+    char* b = static_cast<char*>(storage);
+    tc::GraphDev g;
+    g.meta = reinterpret_cast<tc::GraphMeta*>(b + L.s_meta);
+    g.off = reinterpret_cast<int64_t*>(b + L.s_off);
+    g.col = reinterpret_cast<uint32_t*>(b + L.s_col);
+    g.rank = reinterpret_cast<uint32_t*>(b + L.s_rank);
+    g.items = reinterpret_cast<uint32_t*>(b + L.s_items);
+    return g;
+}
+
+tc::BuildTemp temp_ptrs(void* temp, const Layout& L) {
+    char* b = static_cast<char*>(temp);
+    tc::BuildTemp t;
+    t.keys_a = reinterpret_cast<unsigned long long*>(b + L.t_keys_a);
+    t.keys_b = reinterpret_cast<unsigned long long*>(b + L.t_keys_b);
+    t.deg = reinterpret_cast<uint32_t*>(b + L.t_deg);
+    t.dplus = reinterpret_cast<uint32_t*>(b + L.t_dplus);
+    t.order = reinterpret_cast<uint32_t*>(b + L.t_order);
+    t.skey_a = reinterpret_cast<unsigned long long*>(b + L.t_skey_a);
+    t.skey_b = reinterpret_cast<unsigned long long*>(b + L.t_skey_b);
+    t.sort_tmp = b + L.t_sort;
+    t.sort_tmp_bytes = L.sort_tmp_bytes;
+    return t;
+}
+
+tc_status check_sizes(tc_context* ctx, uint64_t m_in) {
+    if (m_in >= (1ull << 31)) return fail(ctx, TC_E_UNSUPPORTED, "m_in = %llu exceeds 2^31 - 1", (unsigned long long)m_in);
+    return TC_OK;
+}
+
+tc_status use_device(tc_context* ctx) {
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    return TC_OK;
+}
+
+tc_status build_into(tc_context* ctx, tc_graph* g, uint32_t n, uint64_t m_in, const uint32_t* src,
+                     const uint32_t* dst, void* storage, void* temp, const Layout& L, hipStream_t s) {
+    g->ctx = ctx;
+    g->n = n;
+    g->m_in = m_in;
+    g->p = ctx->p;
+    g->caps = bin_caps(ctx->p);
+    g->empty = (n == 0 || m_in == 0);
+    if (g->empty) {
+        g->dev = tc::GraphDev{};
+        if (storage) {
+            g->dev = graph_ptrs(storage, L);
+            HIP_TRY(ctx, tc::fill_u32(g->dev.meta, 0, sizeof(tc::GraphMeta) / 4, s));
+            HIP_TRY(ctx, tc::fill_u32(g->dev.off, 0, 2 * ((size_t)n + 1), s));
+            HIP_TRY(ctx, tc::fill_u32(g->dev.rank, 0, n, s));
+        }
+        return TC_OK;
+    }
+    g->dev = graph_ptrs(storage, L);
+    if (ctx->timing) HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
+    HIP_TRY(ctx, tc::prep_build(n, m_in, src, dst, g->dev, temp_ptrs(temp, L), g->caps, g->p.slots_per_bucket,
+                                g->p.load_factor_pct, s));
+    if (ctx->timing) {
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
+        ctx->have_build = true;
+    }
+    return TC_OK;
+}
+
+tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_total, uint64_t* d_per_vertex, void* scratch,
+                     const Layout& L, hipStream_t s) {
+    const tc_params& p = g->p;
+    const bool pv = d_per_vertex != nullptr;
+    char* b = static_cast<char*>(scratch);
+    if (g->empty) {
+        HIP_TRY(ctx, tc::fill_u32(d_total, 0, 2, s));
+        if (pv) HIP_TRY(ctx, tc::fill_u32(d_per_vertex, 0, 2 * (size_t)g->n, s));
+        return TC_OK;
+    }
+    tc::CountArgs a{};
+    a.meta = g->dev.meta;
+    a.off = g->dev.off;
+    a.col = g->dev.col;
+    a.items = g->dev.items;
+    a.heads = reinterpret_cast<uint32_t*>(b + L.c_heads);
+    a.total = reinterpret_cast<unsigned long long*>(d_total);
+    a.tv = pv ? reinterpret_cast<unsigned long long*>(b + L.c_tv) : nullptr;
+    a.hub_scratch = reinterpret_cast<uint32_t*>(b + L.c_hub);
+    a.hub_words = L.hub_words;
+    a.hub_wgs = L.hub_wgs;
+    a.slice_words = slice_words(p);
+    a.load_pct = p.load_factor_pct;
+    a.chunk = p.light_chunk;
+    const uint32_t threads = 64 * p.wg_waves;
+    int per_cu = 0;
+    HIP_TRY(ctx, tc::count_kernel_info(p.slots_per_bucket, pv, p.hash_kind, threads, p.wg_lds_bytes, &per_cu));
+    if (per_cu < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, p.wg_lds_bytes);
+    uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu * ctx->cu_count);
+    if (grid < a.hub_wgs) a.hub_wgs = grid;
+    HIP_TRY(ctx, tc::fill_u32(a.heads, 0, 4, s));
+    HIP_TRY(ctx, tc::fill_u32(d_total, 0, 2, s));
+    if (pv) HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * (size_t)g->n, s));
+    if (ctx->timing) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
+    HIP_TRY(ctx, tc::count_launch(p.slots_per_bucket, pv, p.hash_kind, grid, threads, p.wg_lds_bytes, a, s));
+    if (ctx->timing) {
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
+        ctx->have_count = true;
+    }
+    if (pv) HIP_TRY(ctx, tc::gather_per_vertex(a.tv, g->dev.rank, g->n, reinterpret_cast<unsigned long long*>(d_per_vertex), s));
+    return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tc_status_str(tc_status s) {
+    switch (s) {
+        case TC_OK: return "ok";
+        case TC_E_INVALID: return "invalid argument";
+        case TC_E_RANGE: return "vertex id out of range";
+        case TC_E_NOMEM: return "workspace too small";
+        case TC_E_DEVICE: return "device error";
+        case TC_E_UNSUPPORTED: return "unsupported size";
+        case TC_E_BUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+const char* tc_last_error(const tc_context* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+tc_status tc_default_params(tc_params* p) {
+    if (!p) return TC_E_INVALID;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(tc_params);
+    p->wg_waves = 8;
+    p->wg_lds_bytes = 65536;
+    p->wave_max_dplus = 0;
+    p->slots_per_bucket = 2;
+    p->load_factor_pct = 50;
+    p->hash_kind = 0;
+    p->light_chunk = 4;
+    p->grid_wgs = 0;
+    p->flags = 0;
+    return TC_OK;
+}
+
+tc_status tc_create(int hip_device, const tc_params* p, tc_context** out) {
+    if (!out) return TC_E_INVALID;
+    *out = nullptr;
+    tc_params q;
+    if (p) q = *p; else tc_default_params(&q);
+    if (check_params(&q) != TC_OK) return TC_E_INVALID;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return TC_E_DEVICE;
+    if (hip_device < 0 || hip_device >= count) return TC_E_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return TC_E_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TC_E_DEVICE;
+    tc_context* c = new (std::nothrow) tc_context();
+    if (!c) return TC_E_NOMEM;
+    c->device = hip_device;
+    c->cu_count = prop.multiProcessorCount;
+    c->lds_per_block_max = prop.sharedMemPerBlock;
+    c->p = q;
+    *out = c;
+    return TC_OK;
+}
+
+tc_status tc_destroy(tc_context* ctx) {
+    if (!ctx) return TC_OK;
+    for (hipEvent_t& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return TC_OK;
+}
+
+tc_status tc_timing_enable(tc_context* ctx, int on) {
+    if (!ctx) return TC_E_INVALID;
+    if (on && !ctx->ev[0]) {
+        if (tc_status s = use_device(ctx)) return s;
+        for (hipEvent_t& e : ctx->ev) HIP_TRY(ctx, hipEventCreate(&e));
+    }
+    ctx->timing = on != 0;
+    ctx->have_build = ctx->have_count = false;
+    return TC_OK;
+}
+
+tc_status tc_timing_last(tc_context* ctx, float* build_ms, float* count_kernel_ms) {
+    if (!ctx || !build_ms || !count_kernel_ms) return TC_E_INVALID;
+    *build_ms = -1.0f;
+    *count_kernel_ms = -1.0f;
+    if (!ctx->timing) return TC_OK;
+    if (ctx->have_build) {
+        HIP_TRY(ctx, hipEventSynchronize(ctx->ev[1]));
+        HIP_TRY(ctx, hipEventElapsedTime(build_ms, ctx->ev[0], ctx->ev[1]));
+    }
+    if (ctx->have_count) {
+        HIP_TRY(ctx, hipEventSynchronize(ctx->ev[3]));
+        HIP_TRY(ctx, hipEventElapsedTime(count_kernel_ms, ctx->ev[2], ctx->ev[3]));
+    }
+    return TC_OK;
+}
+
+tc_status tc_set_params(tc_context* ctx, const tc_params* p) {
+    if (!ctx) return TC_E_INVALID;
+    if (check_params(p) != TC_OK) return fail(ctx, TC_E_INVALID, "invalid tc_params");
+    ctx->p = *p;
+    return TC_OK;
+}
+
+tc_status tc_get_params(const tc_context* ctx, tc_params* out) {
+    if (!ctx || !out) return TC_E_INVALID;
+    *out = ctx->p;
+    return TC_OK;
+}
+
+tc_status tc_workspace_bytes(const tc_context* ctx, uint32_t n, uint64_t m_in, uint64_t* bytes) {
+    if (!ctx || !bytes) return TC_E_INVALID;
+    if (m_in >= (1ull << 31)) return TC_E_UNSUPPORTED;
+    const Layout L = layout(ctx, ctx->p, n, m_in);
+    *bytes = L.storage + L.temp + L.scratch;
+    return TC_OK;
+}
+
+tc_status tc_graph_footprint(const tc_context* ctx, uint32_t n, uint64_t m_in, uint64_t* storage_bytes,
+                             uint64_t* temp_bytes) {
+    if (!ctx || !storage_bytes || !temp_bytes) return TC_E_INVALID;
+    if (m_in >= (1ull << 31)) return TC_E_UNSUPPORTED;
+    const Layout L = layout(ctx, ctx->p, n, m_in);
+    *storage_bytes = L.storage;
+    *temp_bytes = L.temp;
+    return TC_OK;
+}
+
+tc_status tc_count_scratch_bytes(const tc_context* ctx, uint32_t n, uint64_t m_in, uint64_t* bytes) {
+    if (!ctx || !bytes) return TC_E_INVALID;
+    if (m_in >= (1ull << 31)) return TC_E_UNSUPPORTED;
+    *bytes = layout(ctx, ctx->p, n, m_in).scratch;
+    return TC_OK;
+}
+
+tc_status tc_count(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d_src, const uint32_t* d_dst,
+                   uint64_t* d_per_vertex, void* d_ws, uint64_t ws_bytes, void* stream, uint64_t* h_total) {
+    if (!ctx || !h_total) return TC_E_INVALID;
+    ctx->err.clear();
+    if (m_in && (!d_src || !d_dst)) return fail(ctx, TC_E_INVALID, "null edge arrays");
+    if (tc_status s = check_sizes(ctx, m_in)) return s;
+    const Layout L = layout(ctx, ctx->p, n, m_in);
+    const uint64_t need = L.storage + L.temp + L.scratch;
+    if (!d_ws || ws_bytes < need)
+        return fail(ctx, TC_E_NOMEM, "workspace %llu bytes < %llu needed", (unsigned long long)ws_bytes,
+                    (unsigned long long)need);
+    if (tc_status s = use_device(ctx)) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(d_ws);
+    tc_graph g;
+    if (tc_status s = build_into(ctx, &g, n, m_in, d_src, d_dst, ws, ws + L.storage, L, st)) return s;
+    void* scratch = ws + L.storage + L.temp;
+    uint64_t* d_total = reinterpret_cast<uint64_t*>(static_cast<char*>(scratch) + L.c_total);
+    if (tc_status s = count_into(ctx, &g, d_total, d_per_vertex, scratch, L, st)) return s;
+    uint64_t host[2] = {0, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(&host[0], d_total, 8, hipMemcpyDeviceToHost, st));
+    unsigned int err = 0;
+    if (!g.empty) HIP_TRY(ctx, hipMemcpyAsync(&err, &g.dev.meta->err, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (err & 1u) return fail(ctx, TC_E_RANGE, "an input vertex id is >= n = %u", n);
+    *h_total = host[0];
+    return TC_OK;
+}
+
+tc_status tc_graph_build(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d_src, const uint32_t* d_dst,
+                         void* d_storage, uint64_t storage_bytes, void* d_temp, uint64_t temp_bytes, void* stream,
+                         tc_graph** out) {
+    if (!ctx || !out) return TC_E_INVALID;
+    *out = nullptr;
+    ctx->err.clear();
+    if (m_in && (!d_src || !d_dst)) return fail(ctx, TC_E_INVALID, "null edge arrays");
+    if (tc_status s = check_sizes(ctx, m_in)) return s;
+    const Layout L = layout(ctx, ctx->p, n, m_in);
+    if (!d_storage || storage_bytes < L.storage) return fail(ctx, TC_E_NOMEM, "storage too small");
+    if (L.temp && (!d_temp || temp_bytes < L.temp)) return fail(ctx, TC_E_NOMEM, "temp too small");
+    if (tc_status s = use_device(ctx)) return s;
+    tc_graph* g = new (std::nothrow) tc_graph();
+    if (!g) return TC_E_NOMEM;
+    tc_status s = build_into(ctx, g, n, m_in, d_src, d_dst, d_storage, d_temp, L, static_cast<hipStream_t>(stream));
+    if (s != TC_OK) { delete g; return s; }
+    *out = g;
+    return TC_OK;
+}
+
+tc_status tc_graph_count(tc_context* ctx, const tc_graph* g, uint64_t* d_total, uint64_t* d_per_vertex,
+                         void* d_scratch, uint64_t scratch_bytes, void* stream) {
+    if (!ctx || !g || !d_total) return TC_E_INVALID;
+    ctx->err.clear();
+    const Layout L = layout(ctx, g->p, g->n, g->m_in);
+    if (!d_scratch || scratch_bytes < L.scratch) return fail(ctx, TC_E_NOMEM, "scratch too small");
+    if (tc_status s = use_device(ctx)) return s;
+    return count_into(ctx, g, d_total, d_per_vertex, d_scratch, L, static_cast<hipStream_t>(stream));
+}
+
+tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out) {
+    if (!g || !out) return TC_E_INVALID;
+    std::memset(out, 0, sizeof(*out));
+    out->n = g->n;
+    out->wave_cap = g->caps.wave_cap;
+    out->wg_cap = g->caps.wg_cap;
+    if (g->empty) return TC_OK;
+    tc::GraphMeta m;
+    if (hipSetDevice(g->ctx->device) != hipSuccess) return TC_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(&m, g->dev.meta, sizeof(m), hipMemcpyDeviceToHost, st) != hipSuccess) return TC_E_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return TC_E_DEVICE;
+    out->m = m.m;
+    out->wedges_plus = m.wplus;
+    out->max_dplus = m.max_dplus;
+    out->n_hub = m.bins[0];
+    out->n_wg = m.bins[1];
+    out->n_wave = m.bins[2];
+    if (m.err & 1u) return TC_E_RANGE;
+    return TC_OK;
+}
+
+tc_status tc_graph_release(tc_graph* g) {
+    delete g;
+    return TC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,341 @@
+// The counting kernel: vertex-centric hashing (paper Section 3, Algorithm 1)
+// on the oriented rank-space CSR, for gfx950.
+//
+// One persistent launch.  A "group" owns one vertex u at a time:
+//   * hub bin      : the whole workgroup, table in a global-memory region of
+//                    its own (out-degree too large for LDS);
+//   * workgroup bin: the whole workgroup, table in the workgroup's LDS;
+//   * wavefront bin: one 64-lane wavefront, table in its slice of the LDS.
+// This is the degree-aware resource assignment of Section 4.3 (a CTA for
+// large vertices, a warp for small ones; vertices with fewer than two
+// out-neighbours skipped), with atomic dynamic work fetching (one vertex per
+// fetch for workgroups, `chunk` vertices per fetch for wavefronts).
+//
+// Per vertex u (d = d+(u) out-neighbours):
+//   build  : buckets B (power of two), S slots each, len[] counters.  Every
+//            w in N+(u) takes a slot with an atomic add on len[hash(w)]
+//            (Algorithm 1, hashTableConstruction); a full bucket passes the
+//            element on to the next bucket (the linear-probing overflow rule
+//            of Section 3.2).  Slots of a bucket are contiguous, so one
+//            8- or 16-byte LDS read fetches a whole bucket; unused slots hold
+//            0xFFFFFFFF, which ends a probe.
+//   records: for each out-neighbour v_k, its 2-hop list start and the
+//            inclusive prefix of d+(v_k) (virtual combination, Section 4.2):
+//            flattened 2-hop index i belongs to the first k whose prefix
+//            exceeds i, at local offset i - exclusive prefix.
+//   probe  : lanes walk the flattened 2-hop index space 64 at a time, so
+//            consecutive lanes read consecutive words of the same list
+//            (coalesced); each lane keeps a cursor (k, end, base) that only
+//            moves forward.  Each w is looked up in its bucket (Algorithm 1,
+//            intersection / linearSearch); a hit is one triangle (u, v_k, w).
+//   reduce : the wavefront's hit mask is counted with one ballot + popcount
+//            (a wave-wide reduction on the scalar unit), accumulated per
+//            wavefront, summed across the workgroup in LDS and added to the
+//            total with one atomic per workgroup at the end.
+// Per-vertex mode adds, per hit, LDS tallies for the matched slot's element
+// (w) and for v_k; after the probe, u's hits and the non-zero tallies go to
+// the per-vertex array with one global atomic each.
+#include "tc_internal.h"
+
+namespace tc {
+namespace {
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WG>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (WG) __syncthreads();
+    else wave_sync();
+}
+
+template <int HK>
+__device__ __forceinline__ uint32_t hash_of(uint32_t w, uint32_t B) {
+    if constexpr (HK == 0) return w & (B - 1);
+    else return (uint32_t)(((uint64_t)(w * 0x9E3779B1u) * B) >> 32);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Look w up in the table; on a hit, *slot gets its slot index.
+template <int S, int HK>
+__device__ __forceinline__ bool lookup(const uint32_t* slots, uint32_t w, uint32_t B, uint32_t* slot) {
+    uint32_t b = hash_of<HK>(w, B);
+    for (uint32_t t = 0; t < B; ++t) {
+        uint32_t v[S];
+        if constexpr (S == 1) {
+            v[0] = slots[b];
+        } else if constexpr (S == 2) {
+            const u32x2 x = *reinterpret_cast<const u32x2*>(slots + 2 * b);
+            v[0] = x.x; v[1] = x.y;
+        } else {
+            const u32x4 x = *reinterpret_cast<const u32x4*>(slots + 4 * b);
+            v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        }
+        bool found = false;
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = S - 1; j >= 0; --j)
+            if (v[j] == w) { found = true; s = b * S + j; }
+        if (found) { *slot = s; return true; }
+        if (v[S - 1] == kEmpty) return false;
+        b = (b + 1) & (B - 1);
+    }
+    return false;
+}
+
+constexpr int kUnroll = 4;
+
+// Probe the flattened 2-hop range [lo, hi) of the current vertex with one wavefront.
+template <int S, bool PV, int HK>
+__device__ __forceinline__ unsigned long long probe_range(const uint32_t* __restrict__ col, const uint32_t* slots,
+                                                          const u32x2* P, const uint32_t* selem, uint32_t* tally,
+                                                          uint32_t B, uint32_t d, uint32_t lo, uint32_t hi,
+                                                          int lane) {
+    unsigned long long hits = 0;
+    if (lo >= hi) return 0;
+    uint32_t i = lo + (uint32_t)lane;
+    uint32_t k = 0, end = 0, base = 0;
+    if (i < hi) {  // first k with end[k] > i
+        uint32_t l = 0, r = d - 1;
+        while (l < r) {
+            const uint32_t mid = (l + r) >> 1;
+            if (P[mid].x > i) r = mid; else l = mid + 1;
+        }
+        k = l;
+        const u32x2 rec = P[k];
+        end = rec.x;
+        base = rec.y;
+    }
+    const uint32_t nch = (hi - lo + 63) >> 6;
+    for (uint32_t c = 0; c < nch; c += kUnroll) {
+        uint32_t w[kUnroll], kk[kUnroll];
+        bool act[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const uint32_t ii = i + 64u * j;
+            act[j] = ii < hi;
+            w[j] = kEmpty;
+            kk[j] = 0;
+            if (act[j]) {
+                while (ii >= end) {
+                    ++k;
+                    const u32x2 rec = P[k];
+                    end = rec.x;
+                    base = rec.y;
+                }
+                w[j] = col[(uint32_t)(base + ii)];
+                kk[j] = k;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            uint32_t s = 0;
+            const bool hit = act[j] && lookup<S, HK>(slots, w[j], B, &s);
+            hits += (unsigned long long)__popcll(__ballot(hit));
+            if constexpr (PV) {
+                if (hit) {
+                    atomicAdd(&tally[selem[s]], 1u);
+                    atomicAdd(&tally[kk[j]], 1u);
+                }
+            }
+        }
+        i += 64u * kUnroll;
+    }
+    return hits;
+}
+
+// Process vertex u with a group of `gsz` lanes (one wavefront, or the workgroup when WG).
+template <int S, bool PV, int HK, bool WG>
+__device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t* tbl, int gl, int gsz, int gwave,
+                                        int gnw, int lane, uint32_t* s_wsum, unsigned long long& acc) {
+    const int64_t beg = a.off[u];
+    const uint32_t d = (uint32_t)(a.off[u + 1] - beg);
+    const Geometry g = geometry(d, S, a.load_pct, PV);
+    uint32_t* slots = tbl;
+    uint32_t* len = tbl + g.o_len;
+    u32x2* P = reinterpret_cast<u32x2*>(tbl + g.o_P);
+    uint32_t* selem = tbl + g.o_selem;
+    uint32_t* tally = tbl + g.o_tally;
+
+    for (uint32_t x = gl; x < g.B * S; x += gsz) slots[x] = kEmpty;
+    for (uint32_t x = gl; x < g.B; x += gsz) len[x] = 0;
+    if constexpr (PV)
+        for (uint32_t x = gl; x < d; x += gsz) tally[x] = 0;
+    group_sync<WG>();
+
+    // Build the table of N+(u); record each out-neighbour's 2-hop list (length, start).
+    for (uint32_t p = gl; p < d; p += gsz) {
+        const uint32_t w = a.col[beg + p];
+        uint32_t b = hash_of<HK>(w, g.B), pos;
+        for (;;) {
+            pos = atomicAdd(&len[b], 1u);
+            if (pos < (uint32_t)S) break;
+            b = (b + 1) & g.mask;
+        }
+        slots[b * S + pos] = w;
+        if constexpr (PV) selem[b * S + pos] = p;
+        const int64_t o0 = a.off[w], o1 = a.off[w + 1];
+        P[p] = u32x2{(uint32_t)(o1 - o0), (uint32_t)o0};
+    }
+    group_sync<WG>();
+
+    // Inclusive prefix of the 2-hop lengths; base = start - exclusive prefix (mod 2^32).
+    uint32_t carry = 0;
+    for (uint32_t t0 = 0; t0 < d; t0 += gsz) {
+        const uint32_t p = t0 + gl;
+        u32x2 r = u32x2{0u, 0u};
+        if (p < d) r = P[p];
+        uint32_t incl = wave_incl_scan(r.x, lane), tot;
+        if constexpr (WG) {
+            if (lane == 63) s_wsum[gwave] = incl;
+            __syncthreads();
+            uint32_t pre = 0;
+            tot = 0;
+            for (int w = 0; w < gnw; ++w) {
+                const uint32_t t = s_wsum[w];
+                if (w < gwave) pre += t;
+                tot += t;
+            }
+            __syncthreads();
+            incl += pre;
+        } else {
+            tot = __shfl(incl, 63, 64);
+        }
+        if (p < d) {
+            const uint32_t e = carry + incl;
+            P[p] = u32x2{e, r.y - (e - r.x)};
+        }
+        carry += tot;
+    }
+    group_sync<WG>();
+
+    // Probe: the group's wavefronts split [0, W) into contiguous ranges.
+    const uint32_t W = carry;
+    const uint32_t lo = (uint32_t)(((uint64_t)W * gwave) / gnw);
+    const uint32_t hi = (uint32_t)(((uint64_t)W * (gwave + 1)) / gnw);
+    const unsigned long long hits = probe_range<S, PV, HK>(a.col, slots, P, selem, tally, g.B, d, lo, hi, lane);
+    acc += hits;
+
+    if constexpr (PV) {
+        if (lane == 0 && hits) atomicAdd(&a.tv[u], hits);
+        group_sync<WG>();
+        for (uint32_t p = gl; p < d; p += gsz) {
+            const uint32_t t = tally[p];
+            if (t) atomicAdd(&a.tv[a.col[beg + p]], (unsigned long long)t);
+        }
+    }
+    group_sync<WG>();  // the table memory is reused by the next vertex
+}
+
+template <int S, bool PV, int HK>
+__global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ uint32_t s_wsum[kMaxWaves];
+    __shared__ unsigned long long s_acc[kMaxWaves];
+    __shared__ uint32_t s_item;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    unsigned long long acc = 0;
+    const uint32_t n_hub = a.meta->bins[0], n_wg = a.meta->bins[1], n_wave = a.meta->bins[2];
+
+    // Hub bin: global-memory tables, one region per participating workgroup.
+    if (blockIdx.x < a.hub_wgs && n_hub) {
+        uint32_t* gt = a.hub_scratch + (size_t)blockIdx.x * a.hub_words;
+        for (;;) {
+            if (tid == 0) s_item = atomicAdd(&a.heads[0], 1u);
+            __syncthreads();
+            const uint32_t j = s_item;
+            __syncthreads();
+            if (j >= n_hub) break;
+            process<S, PV, HK, true>(a, a.items[j], gt, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
+        }
+    }
+    // Workgroup bin: the table fills the workgroup's LDS.
+    if (n_wg) {
+        for (;;) {
+            if (tid == 0) s_item = atomicAdd(&a.heads[1], 1u);
+            __syncthreads();
+            const uint32_t j = s_item;
+            __syncthreads();
+            if (j >= n_wg) break;
+            process<S, PV, HK, true>(a, a.items[n_hub + j], lds, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
+        }
+    }
+    // Wavefront bin: each wavefront owns a slice of the LDS.
+    {
+        uint32_t* slice = lds + (size_t)wave * a.slice_words;
+        const uint32_t base = n_hub + n_wg;
+        for (;;) {
+            uint32_t j0 = 0;
+            if (lane == 0) j0 = atomicAdd(&a.heads[2], a.chunk);
+            j0 = __builtin_amdgcn_readfirstlane(j0);
+            if (j0 >= n_wave) break;
+            const uint32_t j1 = (j0 + a.chunk < n_wave) ? j0 + a.chunk : n_wave;
+            for (uint32_t j = j0; j < j1; ++j)
+                process<S, PV, HK, false>(a, a.items[base + j], slice, lane, 64, 0, 1, lane, nullptr, acc);
+        }
+    }
+
+    if (lane == 0) s_acc[wave] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long sum = 0;
+        for (int w = 0; w < nw; ++w) sum += s_acc[w];
+        if (sum) atomicAdd(a.total, sum);
+    }
+}
+
+typedef void (*KernelFn)(CountArgs);
+
+template <int S>
+KernelFn pick_hk(bool pv, uint32_t hk) {
+    if (pv) return hk ? tc_count_kernel<S, true, 1> : tc_count_kernel<S, true, 0>;
+    return hk ? tc_count_kernel<S, false, 1> : tc_count_kernel<S, false, 0>;
+}
+
+KernelFn pick(uint32_t S, bool pv, uint32_t hk) {
+    switch (S) {
+        case 1: return pick_hk<1>(pv, hk);
+        case 2: return pick_hk<2>(pv, hk);
+        case 4: return pick_hk<4>(pv, hk);
+        default: return nullptr;
+    }
+}
+
+}  // namespace
+
+hipError_t count_kernel_info(uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads, uint32_t lds_bytes,
+                             int* blocks_per_cu) {
+    KernelFn f = pick(S, pv, hash_kind);
+    if (!f) return hipErrorInvalidValue;
+    if (lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(f),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void*>(f),
+                                                        (int)threads, (size_t)lds_bytes);
+}
+
+hipError_t count_launch(uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
+                        uint32_t lds_bytes, const CountArgs& a, hipStream_t stream) {
+    KernelFn f = pick(S, pv, hash_kind);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(threads), lds_bytes, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace tc

@@ -1,0 +1,139 @@
+// Internal declarations of the device path (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "trust_tc.h"
+
+namespace tc {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash slot; never a valid id (ids < n <= 2^32 - 1)
+constexpr uint32_t kMaxWaves = 16;
+constexpr uint32_t kHubWgs = 128;        // workgroups that take global-memory-table vertices
+
+// Device-resident summary of a built graph (first 256 bytes of its storage).
+struct GraphMeta {
+    unsigned long long m;           // oriented edges
+    unsigned long long wplus;       // W+ = sum over oriented (u, v) of d+(v)
+    unsigned int m_unique;          // distinct keys after dedup (may include the removed-edge sentinel)
+    unsigned int max_dplus;
+    unsigned int err;               // bit 0: some input id >= n
+    unsigned int bins[4];           // vertex counts: hub, workgroup, wavefront, skipped (d+ < 2 or no 2-hop work)
+    unsigned int pad[53];
+};
+static_assert(sizeof(GraphMeta) == 256, "meta is one 256-byte block");
+
+// Hash-table geometry for a vertex with d out-neighbours, shared by the host
+// (capacity per bin) and the kernels (layout in LDS or in global memory).
+// Layout in 32-bit words:
+//   slots[B*S] | len[B] | pad to 4 | P[2d] | (per-vertex mode) selem[B*S] | tally[d]
+// B is the smallest power of two with B*S > d and B*S*load >= d, so every
+// probe chain ends at a bucket with a free slot.
+struct Geometry {
+    uint32_t B, mask, o_len, o_P, o_selem, o_tally, words;
+};
+
+__host__ __device__ inline uint32_t next_pow2(uint32_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+__host__ __device__ inline Geometry geometry(uint32_t d, uint32_t S, uint32_t load_pct, bool pv) {
+    uint32_t need = (d + S) / S;                                // B*S > d
+    uint32_t c = (uint32_t)(((uint64_t)d * 100 + (uint64_t)S * load_pct - 1) / ((uint64_t)S * load_pct));
+    if (c > need) need = c;
+    Geometry g;
+    g.B = next_pow2(need);
+    g.mask = g.B - 1;
+    g.o_len = g.B * S;
+    g.o_P = (g.o_len + g.B + 3u) & ~3u;
+    g.o_selem = g.o_P + 2 * d;
+    g.o_tally = g.o_selem + (pv ? g.B * S : 0);
+    g.words = (g.o_tally + (pv ? d : 0) + 3u) & ~3u;
+    return g;
+}
+
+// Largest d whose table fits in `words` 32-bit words (0 if none).
+inline uint32_t capacity(uint32_t words, uint32_t S, uint32_t load_pct, bool pv) {
+    uint32_t lo = 0, hi = words;  // words(d) >= 2d, so d <= words / 2
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (geometry(mid, S, load_pct, pv).words <= words) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Pointers into a built graph's storage (rank space: vertex r is the r-th in (degree, id) order).
+struct GraphDev {
+    GraphMeta* meta;
+    int64_t* off;       // [n + 1] CSR offsets of the oriented graph
+    uint32_t* col;      // [m_in] out-neighbour lists (first meta->m entries used)
+    uint32_t* rank;     // [n] input id -> rank
+    uint32_t* items;    // [n] scheduled vertices: hub bin, workgroup bin, wavefront bin, skipped
+};
+
+struct BuildTemp {
+    unsigned long long* keys_a;
+    unsigned long long* keys_b;
+    uint32_t* deg;       // [n + 1]; reused as the fill cursor
+    uint32_t* dplus;     // [n + 1]
+    uint32_t* order;     // [n]
+    unsigned long long* skey_a;  // [n]
+    unsigned long long* skey_b;  // [n]
+    void* sort_tmp;
+    size_t sort_tmp_bytes;
+};
+
+struct BinCaps {
+    uint32_t wave_cap, wg_cap;
+    bool force_wg, force_hub, lpt, sort_lists;
+};
+
+struct Layout {
+    size_t storage, temp, scratch;
+    // storage offsets
+    size_t s_meta, s_off, s_col, s_rank, s_items;
+    // temp offsets
+    size_t t_keys_a, t_keys_b, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_sort;
+    size_t sort_tmp_bytes;
+    // scratch offsets
+    size_t c_tv, c_heads, c_total, c_hub;
+    uint64_t hub_words;
+    uint32_t hub_wgs;
+};
+
+struct CountArgs {
+    const GraphMeta* meta;
+    const int64_t* off;
+    const uint32_t* col;
+    const uint32_t* items;
+    uint32_t* heads;                 // [4] queue heads (zeroed before launch)
+    unsigned long long* total;       // [1] (zeroed before launch)
+    unsigned long long* tv;          // [n] per-vertex counts in rank space, or null
+    uint32_t* hub_scratch;           // hub_wgs * hub_words words
+    unsigned long long hub_words;
+    uint32_t hub_wgs;
+    uint32_t slice_words;            // per-wavefront LDS slice
+    uint32_t load_pct;
+    uint32_t chunk;
+};
+
+// tc_prep.hip
+size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in);
+hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint32_t* dst,
+                      const GraphDev& g, const BuildTemp& t, const BinCaps& caps, uint32_t S,
+                      uint32_t load_pct, hipStream_t stream);
+hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream);
+hipError_t gather_per_vertex(const unsigned long long* tv_rank, const uint32_t* rank, uint32_t n,
+                             unsigned long long* out, hipStream_t stream);
+
+// tc_count.hip
+hipError_t count_kernel_info(uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
+                             uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t count_launch(uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
+                        uint32_t lds_bytes, const CountArgs& a, hipStream_t stream);
+
+}  // namespace tc

@@ -1,0 +1,272 @@
+// Device preprocessing: clean, orient and lay out the graph, then bin its vertices.
+//
+//  1. canonicalise: each sample (a, b) becomes the key (min << nb) | max;
+//     self-loops and out-of-range ids become a sentinel that sorts last
+//     (cleaning rules of the paper, Section 2.6: duplicates and self-loops
+//     removed, directed pairs read as undirected);
+//  2. radix sort + unique: the undirected edge set;
+//  3. degree of every vertex, then its rank in (degree, id) order;
+//  4. orientation by rank-by-degree (Section 2.2): the edge runs from the
+//     lower-ranked to the higher-ranked endpoint, and every id is replaced by
+//     its rank, so out-neighbour lists hold ranks and hashing the low bits of
+//     a rank spreads neighbours of similar degree over consecutive buckets
+//     (the reordering idea of Section 4.1);
+//  5. CSR by counting sort (int64 offsets);
+//  6. scheduling (Section 4.3): out-degree d+ and collective work
+//     W(u) = sum of d+(v) over out-neighbours v (the collective degree of
+//     Equation 2); vertices with d+ < 2 or W = 0 are skipped, the rest go to
+//     a global-memory-table bin, a workgroup bin or a wavefront bin by d+,
+//     and each bin is ordered by decreasing W (largest work first).
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
+#include "tc_internal.h"
+
+namespace tc {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline uint32_t grid_for(uint64_t items) {
+    uint64_t g = (items + kThreads - 1) / kThreads;
+    if (g > 65536) g = 65536;
+    if (g == 0) g = 1;
+    return (uint32_t)g;
+}
+
+inline uint32_t id_bits(uint32_t n) {  // bits to hold any id < n (at least 1)
+    uint32_t b = 1;
+    while (b < 32 && (1ull << b) < (uint64_t)n) ++b;
+    return b;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t words) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_canon(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst, uint64_t m_in,
+                        uint32_t n, uint32_t nb, unsigned long long sentinel,
+                        unsigned long long* __restrict__ keys, GraphMeta* meta) {
+    uint32_t bad = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < m_in; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t a = src[i], b = dst[i];
+        unsigned long long k;
+        if (a >= n || b >= n) { bad = 1; k = sentinel; }
+        else if (a == b) k = sentinel;
+        else {
+            const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+            k = ((unsigned long long)lo << nb) | hi;
+        }
+        keys[i] = k;
+    }
+    if (bad) atomicOr(&meta->err, 1u);
+}
+
+// m = number of distinct keys minus the sentinel (present at most once, last).
+__global__ void k_fix_m(const unsigned long long* keys, unsigned long long sentinel, GraphMeta* meta) {
+    uint32_t u = meta->m_unique;
+    if (u > 0 && keys[u - 1] == sentinel) --u;
+    meta->m = u;
+}
+
+__global__ void k_degree(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
+                         const GraphMeta* meta, uint32_t* __restrict__ deg) {
+    const uint64_t m = meta->m;
+    const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap && i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = keys[i];
+        atomicAdd(&deg[(uint32_t)(k >> nb)], 1u);
+        atomicAdd(&deg[(uint32_t)(k & mask)], 1u);
+    }
+}
+
+__global__ void k_rank(const uint32_t* __restrict__ order, uint32_t n, uint32_t* __restrict__ rank) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        rank[order[r]] = r;
+}
+
+__global__ void k_orient_count(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
+                               const GraphMeta* meta, const uint32_t* __restrict__ rank,
+                               uint32_t* __restrict__ dplus) {
+    const uint64_t m = meta->m;
+    const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap && i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = keys[i];
+        const uint32_t ra = rank[(uint32_t)(k >> nb)], rb = rank[(uint32_t)(k & mask)];
+        atomicAdd(&dplus[ra < rb ? ra : rb], 1u);
+    }
+}
+
+__global__ void k_orient_fill(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
+                              const GraphMeta* meta, const uint32_t* __restrict__ rank,
+                              const int64_t* __restrict__ off, uint32_t* __restrict__ cursor,
+                              uint32_t* __restrict__ col) {
+    const uint64_t m = meta->m;
+    const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap && i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = keys[i];
+        const uint32_t ra = rank[(uint32_t)(k >> nb)], rb = rank[(uint32_t)(k & mask)];
+        const uint32_t s = ra < rb ? ra : rb, d = ra < rb ? rb : ra;
+        const uint32_t pos = atomicAdd(&cursor[s], 1u);
+        col[off[s] + pos] = d;
+    }
+}
+
+// One thread per vertex: d+, W(u), bin, and the sort key (bin << 40 | reversed work).
+__global__ void k_schedule(const int64_t* __restrict__ off, const uint32_t* __restrict__ col, uint32_t n,
+                           BinCaps caps, GraphMeta* meta, unsigned long long* __restrict__ skey) {
+    __shared__ unsigned long long s_w;
+    __shared__ unsigned int s_max, s_bins[4];
+    if (threadIdx.x == 0) { s_w = 0; s_max = 0; s_bins[0] = s_bins[1] = s_bins[2] = s_bins[3] = 0; }
+    __syncthreads();
+    const unsigned long long kWorkMax = (1ull << 40) - 1;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int64_t b = off[r], e = off[r + 1];
+        const uint32_t d = (uint32_t)(e - b);
+        unsigned long long w = 0;
+        for (int64_t p = b; p < e; ++p) {
+            const uint32_t v = col[p];
+            w += (unsigned long long)(off[v + 1] - off[v]);
+        }
+        uint32_t bin;
+        if (d < 2 || w == 0) bin = 3;
+        else if (caps.force_hub || d > caps.wg_cap) bin = 0;
+        else if (caps.force_wg || d > caps.wave_cap) bin = 1;
+        else bin = 2;
+        const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
+        skey[r] = ((unsigned long long)bin << 40) | (caps.lpt ? (kWorkMax - wk) : 0ull);
+        atomicAdd(&s_w, w);
+        atomicMax(&s_max, d);
+        atomicAdd(&s_bins[bin], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&meta->wplus, s_w);
+        atomicMax(&meta->max_dplus, s_max);
+        for (int i = 0; i < 4; ++i) atomicAdd(&meta->bins[i], s_bins[i]);
+    }
+}
+
+__global__ void k_gather(const unsigned long long* __restrict__ tv, const uint32_t* __restrict__ rank, uint32_t n,
+                         unsigned long long* __restrict__ out) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x)
+        out[x] = tv[rank[x]];
+}
+
+#define TC_TRY(expr)                        \
+    do {                                    \
+        hipError_t e_ = (expr);             \
+        if (e_ != hipSuccess) return e_;    \
+    } while (0)
+
+}  // namespace
+
+hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream) {
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words)), dim3(kThreads), 0, stream, (uint32_t*)p, value, words);
+    return hipGetLastError();
+}
+
+hipError_t gather_per_vertex(const unsigned long long* tv_rank, const uint32_t* rank, uint32_t n,
+                             unsigned long long* out, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, stream, tv_rank, rank, n, out);
+    return hipGetLastError();
+}
+
+size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
+    size_t best = 0, sz = 0;
+    const uint32_t nb = id_bits(n);
+    unsigned long long* k64 = nullptr;
+    uint32_t* u32p = nullptr;
+    if (rocprim::radix_sort_keys(nullptr, sz, k64, k64, (size_t)m_in, 0, 2 * nb) == hipSuccess && sz > best) best = sz;
+    sz = 0;
+    if (rocprim::unique(nullptr, sz, k64, k64, u32p, (size_t)m_in) == hipSuccess && sz > best) best = sz;
+    sz = 0;
+    if (rocprim::radix_sort_pairs(nullptr, sz, u32p, u32p, rocprim::counting_iterator<uint32_t>(0), u32p,
+                                  (size_t)n, 0, 32) == hipSuccess && sz > best) best = sz;
+    sz = 0;
+    int64_t* i64p = nullptr;
+    if (rocprim::exclusive_scan(nullptr, sz, u32p, i64p, (unsigned long long)0, (size_t)n + 1,
+                                rocprim::plus<unsigned long long>()) == hipSuccess && sz > best) best = sz;
+    sz = 0;
+    if (rocprim::radix_sort_pairs(nullptr, sz, k64, k64, rocprim::counting_iterator<uint32_t>(0), u32p,
+                                  (size_t)n, 0, 42) == hipSuccess && sz > best) best = sz;
+    sz = 0;
+    if (m_in > 0 && n > 0 &&
+        rocprim::segmented_radix_sort_keys(nullptr, sz, u32p, u32p, (unsigned int)m_in, n, i64p, i64p + 1, 0, 32) ==
+            hipSuccess && sz > best) best = sz;
+    return best;
+}
+
+hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint32_t* dst, const GraphDev& g,
+                      const BuildTemp& t, const BinCaps& caps, uint32_t S, uint32_t load_pct,
+                      hipStream_t stream) {
+    (void)S; (void)load_pct;
+    const uint32_t nb = id_bits(n);
+    const unsigned long long sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1);
+    size_t tmp = t.sort_tmp_bytes;
+
+    TC_TRY(fill_u32(g.meta, 0, sizeof(GraphMeta) / 4, stream));
+    TC_TRY(fill_u32(t.deg, 0, (size_t)n + 1, stream));
+    TC_TRY(fill_u32(t.dplus, 0, (size_t)n + 1, stream));
+
+    // 1-2: canonical keys, sort, unique.
+    hipLaunchKernelGGL(k_canon, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, src, dst, m_in, n, nb, sentinel,
+                       t.keys_a, g.meta);
+    TC_TRY(hipGetLastError());
+    tmp = t.sort_tmp_bytes;
+    TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, t.keys_a, t.keys_b, (size_t)m_in, 0, 2 * nb, stream));
+    tmp = t.sort_tmp_bytes;
+    TC_TRY(rocprim::unique(t.sort_tmp, tmp, t.keys_b, t.keys_a, &g.meta->m_unique, (size_t)m_in,
+                           rocprim::equal_to<unsigned long long>(), stream));
+    hipLaunchKernelGGL(k_fix_m, dim3(1), dim3(1), 0, stream, t.keys_a, sentinel, g.meta);
+    TC_TRY(hipGetLastError());
+
+    // 3: degree, rank in (degree, id) order (stable sort keeps ids ascending among equal degrees).
+    hipLaunchKernelGGL(k_degree, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta, t.deg);
+    TC_TRY(hipGetLastError());
+    uint32_t deg_bits = 1;
+    {
+        const uint64_t dmax = (uint64_t)n - 1 < 2 * m_in ? (uint64_t)n - 1 : 2 * m_in;
+        while (deg_bits < 32 && (1ull << deg_bits) <= dmax) ++deg_bits;
+    }
+    uint32_t* deg_sorted = reinterpret_cast<uint32_t*>(t.skey_a);
+    tmp = t.sort_tmp_bytes;
+    TC_TRY(rocprim::radix_sort_pairs(t.sort_tmp, tmp, t.deg, deg_sorted, rocprim::counting_iterator<uint32_t>(0),
+                                     t.order, (size_t)n, 0, deg_bits, stream));
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(n)), dim3(kThreads), 0, stream, t.order, n, g.rank);
+    TC_TRY(hipGetLastError());
+
+    // 4-5: orientation and CSR in rank space.
+    hipLaunchKernelGGL(k_orient_count, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta,
+                       g.rank, t.dplus);
+    TC_TRY(hipGetLastError());
+    tmp = t.sort_tmp_bytes;
+    TC_TRY(rocprim::exclusive_scan(t.sort_tmp, tmp, t.dplus, g.off, (unsigned long long)0, (size_t)n + 1,
+                                   rocprim::plus<unsigned long long>(), stream));
+    TC_TRY(fill_u32(t.deg, 0, (size_t)n + 1, stream));
+    hipLaunchKernelGGL(k_orient_fill, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta,
+                       g.rank, g.off, t.deg, g.col);
+    TC_TRY(hipGetLastError());
+    if (caps.sort_lists) {
+        uint32_t* col_tmp = reinterpret_cast<uint32_t*>(t.keys_b);
+        tmp = t.sort_tmp_bytes;
+        TC_TRY(rocprim::segmented_radix_sort_keys(t.sort_tmp, tmp, g.col, col_tmp, (unsigned int)m_in, n, g.off,
+                                                  g.off + 1, 0, 32, stream));
+        TC_TRY(hipMemcpyAsync(g.col, col_tmp, sizeof(uint32_t) * m_in, hipMemcpyDeviceToDevice, stream));
+    }
+
+    // 6: bins and largest-work-first order.
+    hipLaunchKernelGGL(k_schedule, dim3(grid_for(n)), dim3(kThreads), 0, stream, g.off, g.col, n, caps, g.meta,
+                       t.skey_a);
+    TC_TRY(hipGetLastError());
+    tmp = t.sort_tmp_bytes;
+    TC_TRY(rocprim::radix_sort_pairs(t.sort_tmp, tmp, t.skey_a, t.skey_b, rocprim::counting_iterator<uint32_t>(0),
+                                     g.items, (size_t)n, 0, 42, stream));
+    return hipSuccess;
+}
+
+}  // namespace tc

@@ -1,0 +1,319 @@
+"""Thin ctypes binding of ``libtrust_tc.so`` (declared in ``include/trust_tc.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory (workspace, outputs) and the stream.
+If the library is not built this module raises on import of its entry points;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtrust_tc.so")
+
+TC_OK, TC_E_INVALID, TC_E_RANGE, TC_E_NOMEM, TC_E_DEVICE, TC_E_UNSUPPORTED, TC_E_BUSY = range(7)
+TC_F_NO_LPT, TC_F_FORCE_WG, TC_F_FORCE_HUB, TC_F_SORT_LISTS = 0x1, 0x2, 0x4, 0x8
+
+EXPORTS = [
+    "tc_default_params", "tc_create", "tc_destroy", "tc_set_params", "tc_get_params", "tc_status_str",
+    "tc_last_error", "tc_workspace_bytes", "tc_count", "tc_graph_footprint", "tc_graph_build",
+    "tc_count_scratch_bytes", "tc_graph_count", "tc_graph_info_get", "tc_graph_release",
+    "tc_timing_enable", "tc_timing_last",
+]
+
+
+class TCError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class RangeError(TCError):
+    pass
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "struct_size", "wg_waves", "wg_lds_bytes", "wave_max_dplus", "slots_per_bucket", "load_factor_pct",
+        "hash_kind", "light_chunk", "grid_wgs", "flags")]
+
+
+class _GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("m", ctypes.c_uint64), ("wedges_plus", ctypes.c_uint64),
+                ("max_dplus", ctypes.c_uint32), ("n_hub", ctypes.c_uint32), ("n_wg", ctypes.c_uint32),
+                ("n_wave", ctypes.c_uint32), ("wave_cap", ctypes.c_uint32), ("wg_cap", ctypes.c_uint32)]
+
+
+@dataclass
+class Params:
+    """Tuning knobs (see ``tc_params`` in the header); none changes any count."""
+    wg_waves: int = 8
+    wg_lds_bytes: int = 65536
+    wave_max_dplus: int = 0
+    slots_per_bucket: int = 2
+    load_factor_pct: int = 50
+    hash_kind: int = 0
+    light_chunk: int = 4
+    grid_wgs: int = 0
+    flags: int = 0
+
+    def to_c(self) -> _Params:
+        p = _Params()
+        p.struct_size = ctypes.sizeof(_Params)
+        for f in fields(self):
+            setattr(p, f.name, int(getattr(self, f.name)))
+        return p
+
+    @classmethod
+    def from_c(cls, p: _Params) -> "Params":
+        return cls(**{f.name: int(getattr(p, f.name)) for f in fields(cls)})
+
+
+@dataclass
+class GraphInfo:
+    n: int
+    m: int
+    wedges_plus: int
+    max_dplus: int
+    n_hub: int
+    n_wg: int
+    n_wave: int
+    wave_cap: int
+    wg_cap: int
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2103_08053_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    pp = ctypes.POINTER(_Params)
+    sig = {
+        "tc_default_params": [pp],
+        "tc_create": [i32, pp, ctypes.POINTER(vp)],
+        "tc_destroy": [vp],
+        "tc_set_params": [vp, pp],
+        "tc_get_params": [vp, pp],
+        "tc_workspace_bytes": [vp, u32, u64, ctypes.POINTER(u64)],
+        "tc_count": [vp, u32, u64, vp, vp, vp, vp, u64, vp, ctypes.POINTER(u64)],
+        "tc_graph_footprint": [vp, u32, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
+        "tc_graph_build": [vp, u32, u64, vp, vp, vp, u64, vp, u64, vp, ctypes.POINTER(vp)],
+        "tc_count_scratch_bytes": [vp, u32, u64, ctypes.POINTER(u64)],
+        "tc_graph_count": [vp, vp, vp, vp, vp, u64, vp],
+        "tc_graph_info_get": [vp, vp, ctypes.POINTER(_GraphInfo)],
+        "tc_graph_release": [vp],
+        "tc_timing_enable": [vp, i32],
+        "tc_timing_last": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.tc_status_str.argtypes = [ctypes.c_int]
+    lib.tc_status_str.restype = ctypes.c_char_p
+    lib.tc_last_error.argtypes = [vp]
+    lib.tc_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, ctx=None):
+    if status == TC_OK:
+        return
+    lib = load_library()
+    msg = lib.tc_status_str(status).decode()
+    if ctx is not None:
+        detail = lib.tc_last_error(ctx).decode()
+        if detail:
+            msg = f"{msg}: {detail}"
+    raise (RangeError if status == TC_E_RANGE else TCError)(status, msg)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _edge_tensor(x, device):
+    torch = _torch()
+    t = torch.as_tensor(x)
+    if t.dtype != torch.int32 and t.dtype != torch.uint32:
+        t = t.to(torch.int64)
+        if t.numel() and (int(t.min()) < 0 or int(t.max()) > 0xFFFFFFFF):
+            raise ValueError("vertex ids must fit in uint32")
+        t = t.to(torch.uint32) if hasattr(torch, "uint32") else t.to(torch.int32)
+    return t.to(device).contiguous()
+
+
+class Context:
+    """A library context bound to one HIP device."""
+
+    def __init__(self, device: int = 0, params: Params | None = None):
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        p = (params or Params()).to_c()
+        _check(self.lib.tc_create(device, ctypes.byref(p), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self) -> Params:
+        p = _Params()
+        _check(self.lib.tc_get_params(self.h, ctypes.byref(p)), self.h)
+        return Params.from_c(p)
+
+    @params.setter
+    def params(self, params: Params):
+        p = params.to_c()
+        _check(self.lib.tc_set_params(self.h, ctypes.byref(p)), self.h)
+
+    def timing(self, on: bool = True):
+        """Record HIP events around the build and the count kernel of every call."""
+        _check(self.lib.tc_timing_enable(self.h, 1 if on else 0), self.h)
+
+    def last_times_ms(self) -> tuple[float, float]:
+        """(build ms, count-kernel ms) of the last timed calls (-1 if none)."""
+        b, c = ctypes.c_float(), ctypes.c_float()
+        _check(self.lib.tc_timing_last(self.h, ctypes.byref(b), ctypes.byref(c)), self.h)
+        return b.value, c.value
+
+    def workspace_bytes(self, n: int, m_in: int) -> int:
+        b = ctypes.c_uint64()
+        _check(self.lib.tc_workspace_bytes(self.h, n, m_in, ctypes.byref(b)), self.h)
+        return b.value
+
+    def footprint(self, n: int, m_in: int) -> tuple[int, int]:
+        s, t = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.tc_graph_footprint(self.h, n, m_in, ctypes.byref(s), ctypes.byref(t)), self.h)
+        return s.value, t.value
+
+    def scratch_bytes(self, n: int, m_in: int) -> int:
+        b = ctypes.c_uint64()
+        _check(self.lib.tc_count_scratch_bytes(self.h, n, m_in, ctypes.byref(b)), self.h)
+        return b.value
+
+    def count(self, src, dst, n: int, per_vertex: bool = False, workspace=None, stream=None):
+        """Triangle count of the undirected graph given by edge samples src[i] -- dst[i].
+
+        Returns (total, per_vertex int64 tensor or None).  src/dst: device or host
+        integer tensors/arrays (copied to the device if needed)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        s = _edge_tensor(src, dev)
+        d = _edge_tensor(dst, dev)
+        if s.shape != d.shape:
+            raise ValueError("src and dst differ in length")
+        m_in = s.numel()
+        need = self.workspace_bytes(n, m_in)
+        ws = workspace
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        pv = torch.empty(max(n, 1), dtype=torch.int64, device=dev) if per_vertex else None
+        tot = ctypes.c_uint64()
+        _check(self.lib.tc_count(self.h, n, m_in, _ptr(s), _ptr(d), _ptr(pv), _ptr(ws), ws.numel(),
+                                 _stream_ptr(stream), ctypes.byref(tot)), self.h)
+        return tot.value, (pv[:n] if per_vertex else None)
+
+    def build(self, src, dst, n: int, stream=None) -> "Graph":
+        return Graph(self, src, dst, n, stream=stream)
+
+
+class Graph:
+    """A graph cleaned, oriented and binned once on the device; count it many times."""
+
+    def __init__(self, ctx: Context, src, dst, n: int, stream=None, storage=None, temp=None):
+        torch = _torch()
+        self.ctx = ctx
+        self.n = n
+        dev = torch.device("cuda", ctx.device)
+        s = _edge_tensor(src, dev)
+        d = _edge_tensor(dst, dev)
+        self.m_in = s.numel()
+        sb, tb = ctx.footprint(n, self.m_in)
+        self.storage = storage if storage is not None else torch.empty(max(sb, 1), dtype=torch.uint8, device=dev)
+        tmp = temp if temp is not None else torch.empty(max(tb, 1), dtype=torch.uint8, device=dev)
+        self.scratch = torch.empty(max(ctx.scratch_bytes(n, self.m_in), 1), dtype=torch.uint8, device=dev)
+        self.total_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+        h = ctypes.c_void_p()
+        _check(ctx.lib.tc_graph_build(ctx.h, n, self.m_in, _ptr(s), _ptr(d), _ptr(self.storage),
+                                      self.storage.numel(), _ptr(tmp), tmp.numel(), _stream_ptr(stream),
+                                      ctypes.byref(h)), ctx.h)
+        self.h = h
+        self._keep = (s, d, tmp)  # alive until the build has run on the stream
+        self.info(stream)  # synchronises; raises RangeError on bad ids
+        self._keep = None
+
+    def info(self, stream=None) -> GraphInfo:
+        gi = _GraphInfo()
+        _check(self.ctx.lib.tc_graph_info_get(self.h, _stream_ptr(stream), ctypes.byref(gi)), self.ctx.h)
+        return GraphInfo(**{k: int(getattr(gi, k)) for k, _ in _GraphInfo._fields_})
+
+    def count_async(self, per_vertex_out=None, stream=None):
+        """Launch the count; the total lands in ``self.total_dev`` (device int64)."""
+        _check(self.ctx.lib.tc_graph_count(self.ctx.h, self.h, _ptr(self.total_dev), _ptr(per_vertex_out),
+                                           _ptr(self.scratch), self.scratch.numel(), _stream_ptr(stream)),
+               self.ctx.h)
+
+    def count(self, per_vertex: bool = False, stream=None):
+        torch = _torch()
+        pv = torch.empty(max(self.n, 1), dtype=torch.int64, device=self.storage.device) if per_vertex else None
+        self.count_async(pv, stream)
+        tot = int(self.total_dev.item())
+        return tot, (pv[: self.n] if per_vertex else None)
+
+    def release(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tc_graph_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+_default_ctx = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context(0)
+    return _default_ctx
+
+
+def count(src, dst, n: int, per_vertex: bool = False):
+    """Triangle count (and optional per-vertex counts) on device 0."""
+    return default_context().count(src, dst, n, per_vertex=per_vertex)

@@ -1,0 +1,87 @@
+"""Host-side checks of the C-ABI library (no GPU needed, no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2103_08053_amd import tc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trust_tc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\*?\s+\**(tc_[a-z_]+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tc.load_library()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(tc.EXPORTS) == names
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(tc._Params) == 10 * 4
+    assert ctypes.sizeof(tc._GraphInfo) == 3 * 8 + 6 * 4
+
+
+def test_default_params():
+    lib = tc.load_library()
+    p = tc._Params()
+    assert lib.tc_default_params(ctypes.byref(p)) == tc.TC_OK
+    assert p.struct_size == ctypes.sizeof(tc._Params)
+    d = tc.Params.from_c(p)
+    assert d == tc.Params()  # the binding's defaults mirror the library's
+    assert lib.tc_default_params(None) == tc.TC_E_INVALID
+
+
+def test_status_strings():
+    lib = tc.load_library()
+    for s in range(7):
+        assert lib.tc_status_str(s)
+    assert lib.tc_status_str(99) == b"unknown status"
+    assert lib.tc_last_error(None) == b""
+
+
+@pytest.mark.parametrize("field,value", [
+    ("struct_size", 3), ("wg_waves", 0), ("wg_waves", 17), ("wg_lds_bytes", 1024),
+    ("wg_lds_bytes", 4100), ("slots_per_bucket", 3), ("load_factor_pct", 5), ("load_factor_pct", 101),
+    ("hash_kind", 2), ("light_chunk", 0), ("light_chunk", 300), ("flags", 0x100),
+])
+def test_create_rejects_bad_params_before_touching_a_device(field, value):
+    lib = tc.load_library()
+    p = tc._Params()
+    lib.tc_default_params(ctypes.byref(p))
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    assert lib.tc_create(0, ctypes.byref(p), ctypes.byref(h)) == tc.TC_E_INVALID
+    assert not h.value
+
+
+def test_null_arguments_are_invalid():
+    lib = tc.load_library()
+    b = ctypes.c_uint64()
+    assert lib.tc_workspace_bytes(None, 10, 10, ctypes.byref(b)) == tc.TC_E_INVALID
+    assert lib.tc_create(0, None, None) == tc.TC_E_INVALID
+    assert lib.tc_count(None, 1, 1, None, None, None, None, 0, None, None) == tc.TC_E_INVALID
+    assert lib.tc_graph_count(None, None, None, None, None, 0, None) == tc.TC_E_INVALID
+    assert lib.tc_graph_info_get(None, None, None) == tc.TC_E_INVALID
+    assert lib.tc_destroy(None) == tc.TC_OK
+    assert lib.tc_graph_release(None) == tc.TC_OK
+
+
+def test_no_device_is_reported(monkeypatch):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    lib = tc.load_library()
+    h = ctypes.c_void_p()
+    assert lib.tc_create(0, None, ctypes.byref(h)) == tc.TC_E_DEVICE
+    with pytest.raises(tc.TCError):
+        tc.Context(0)

@@ -1,0 +1,224 @@
+"""Parity of the HIP path against the CPU oracle (bit-exact integer counts).
+
+Every test calls the C-ABI library through its binding.  The expected side is
+the oracle (run here, or stored in golden/expected_counts.json by
+golden/make_expected.py, which calls only the oracle) or a closed form.
+"""
+import json
+import os
+import sys
+from math import comb
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import graphgen.workloads as W
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "expected_counts.json")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2103_08053_amd import Context
+    return Context(0)
+
+
+def gpu_count(ctx, g, per_vertex=True):
+    say(f"[gpu] {g.name} n={g.n} m_in={g.m_in} params={ctx.params}")
+    tot, pv = ctx.count(g.src, g.dst, g.n, per_vertex=per_vertex)
+    return tot, (pv.cpu().numpy().astype(np.uint64) if per_vertex else None)
+
+
+def assert_parity(ctx, g, expect=None):
+    tot, pv = gpu_count(ctx, g)
+    r = oracle.count(g.n, g.src, g.dst, per_vertex=True)
+    assert tot == r.total, (g.name, tot, r.total)
+    assert (pv == r.per_vertex).all(), g.name
+    if expect is not None:
+        assert tot == expect
+    return tot, pv
+
+
+# ----------------------------------------------------------------------------- closed forms
+
+CLOSED = [
+    (gg.complete(3), 1), (gg.complete(4), 4), (gg.complete(50), comb(50, 3)), (gg.complete(300), comb(300, 3)),
+    (gg.complete_bipartite(20, 30), 0), (gg.wheel(5), 4), (gg.wheel(1000), 999),
+    (gg.complete_tripartite(7, 9, 11), 7 * 9 * 11), (gg.complete_tripartite(1, 1, 600), 600),
+    (gg.cocktail_party(40), comb(80, 3) - 40 * 78), (gg.friendship(500), 500),
+    (gg.cycle(3), 1), (gg.cycle(1000), 0), (gg.star(5000), 0), (gg.random_tree(3000, seed=2), 0),
+    (gg.torus3d(12), 0),
+]
+
+
+@pytest.mark.parametrize("g,expect", CLOSED, ids=[g.name for g, _ in CLOSED])
+def test_closed_forms(ctx, g, expect):
+    assert_parity(ctx, g, expect)
+
+
+def test_disjoint_union(ctx):
+    parts = [gg.complete(40), gg.wheel(77), gg.friendship(9), gg.torus3d(5), gg.complete_tripartite(3, 4, 5)]
+    g = gg.disjoint_union(parts)
+    assert_parity(ctx, g, comb(40, 3) + 76 + 9 + 0 + 60)
+
+
+# ----------------------------------------------------------------------------- random and dirty inputs
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_dirty_graphs(ctx, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 3000))
+    m = int(rng.integers(1, 20 * n))
+    g = gg.dirty(gg.erdos_renyi(n, m, seed=seed), seed=seed)
+    assert_parity(ctx, g)
+
+
+@pytest.mark.parametrize("k", [4, 9, 16])
+def test_barabasi_albert(ctx, k):
+    assert_parity(ctx, gg.barabasi_albert(20000, k, seed=k))
+
+
+def test_rmat_scale16_against_stored(ctx):
+    exp = json.load(open(GOLDEN))["rmat16"]
+    g = W.small_rmat()
+    tot, pv = assert_parity(ctx, g, exp["total"])
+    ids = np.array(exp["sample_ids"])
+    assert (pv[ids] == np.array(exp["sample_counts"], dtype=np.uint64)).all()
+
+
+# ----------------------------------------------------------------------------- every code path, same answer
+
+FORCED = [
+    dict(flags=2),                              # every vertex in the workgroup bin
+    dict(flags=4),                              # every vertex in the global-memory table bin
+    dict(wg_lds_bytes=4096, wg_waves=4),        # tiny LDS: most vertices spill to the global-table bin
+    dict(slots_per_bucket=1), dict(slots_per_bucket=4),
+    dict(load_factor_pct=100), dict(load_factor_pct=10),
+    dict(slots_per_bucket=1, load_factor_pct=100, flags=2),   # long probe chains in LDS
+    dict(slots_per_bucket=1, load_factor_pct=100, flags=4),   # long probe chains in global memory
+    dict(hash_kind=1), dict(light_chunk=1), dict(light_chunk=7), dict(flags=1), dict(flags=8),
+    dict(wg_waves=1), dict(wg_waves=4), dict(wg_waves=16, wg_lds_bytes=131072),
+    dict(grid_wgs=3), dict(grid_wgs=1, flags=4), dict(wave_max_dplus=8),
+]
+
+
+@pytest.fixture(scope="module")
+def forced_graphs():
+    return [gg.dirty(gg.rmat(13, 16, seed=3), seed=1), gg.barabasi_albert(5000, 12, seed=5),
+            gg.complete(200)]
+
+
+@pytest.mark.parametrize("kw", FORCED, ids=[str(k) for k in FORCED])
+def test_forced_paths_agree(torch, forced_graphs, kw):
+    from paper_2103_08053_amd import Context, Params
+    c = Context(0, Params(**kw))
+    for g in forced_graphs:
+        assert_parity(c, g)
+
+
+def test_bins_are_exercised(torch):
+    """A low wavefront cap routes a skewed graph through both LDS bins, and
+    the tiny-LDS parameters route it through the global-table bin."""
+    from paper_2103_08053_amd import Context, Params
+    g = gg.rmat(14, 16, seed=1)
+    info = Context(0, Params(wave_max_dplus=32)).build(g.src, g.dst, g.n).info()
+    assert info.n_wg > 0 and info.n_wave > 0 and info.n_hub == 0
+    small = Context(0, Params(wg_lds_bytes=4096, wg_waves=4)).build(g.src, g.dst, g.n).info()
+    assert small.n_hub > 0
+
+
+# ----------------------------------------------------------------------------- edge cases
+
+def test_empty_inputs(ctx, torch):
+    e = np.zeros(0, np.uint32)
+    assert ctx.count(e, e, 0)[0] == 0
+    tot, pv = ctx.count(e, e, 10, per_vertex=True)
+    assert tot == 0 and int(pv.abs().sum()) == 0
+    loops = np.arange(100, dtype=np.uint32)
+    tot, pv = ctx.count(loops, loops, 100, per_vertex=True)
+    assert tot == 0 and int(pv.abs().sum()) == 0
+    tot, pv = ctx.count(np.array([0], np.uint32), np.array([1], np.uint32), 2, per_vertex=True)
+    assert tot == 0
+
+
+def test_large_id_space(ctx):
+    """Ids near the top of a 2^27 + 5 id space (28-bit ids, 56-bit sort keys)."""
+    n = 2**27 + 5
+    a = np.array([n - 1, n - 2, n - 3, 0, n - 1], np.uint32)
+    b = np.array([n - 2, n - 3, n - 1, n - 1, 0], np.uint32)
+    tot, pv = ctx.count(a, b, n, per_vertex=True)
+    assert tot == 1
+    pv = pv.cpu().numpy()
+    assert pv[n - 1] == 1 and pv[n - 2] == 1 and pv[n - 3] == 1 and pv[0] == 0 and int(pv.sum()) == 3
+
+
+def test_out_of_range_ids_rejected(ctx):
+    from paper_2103_08053_amd import RangeError
+    with pytest.raises(RangeError):
+        ctx.count(np.array([0, 1, 5], np.uint32), np.array([1, 2, 0], np.uint32), 5)
+    # the context stays usable
+    assert ctx.count(np.array([0, 1, 2], np.uint32), np.array([1, 2, 0], np.uint32), 3)[0] == 1
+
+
+def test_unsupported_size(ctx):
+    from paper_2103_08053_amd import TCError
+    with pytest.raises(TCError):
+        ctx.workspace_bytes(100, 2**31)
+
+
+def test_deterministic_repeats(ctx):
+    g = W.small_rmat()
+    graph = ctx.build(g.src, g.dst, g.n)
+    t0, p0 = graph.count(per_vertex=True)
+    for _ in range(20):
+        t, p = graph.count(per_vertex=True)
+        assert t == t0
+        assert bool((p == p0).all())
+    assert graph.count(per_vertex=False)[0] == t0
+
+
+def test_graph_info_matches_oracle(ctx):
+    g = gg.dirty(gg.rmat(14, 16, seed=4), seed=2)
+    info = ctx.build(g.src, g.dst, g.n).info()
+    r = oracle.count(g.n, g.src, g.dst)
+    assert (info.m, info.wedges_plus, info.max_dplus) == (r.m, r.wedges_plus, r.max_dplus)
+
+
+# ----------------------------------------------------------------------------- full-size workload
+
+def test_rmat_scale22_full_size(ctx, torch):
+    """The throughput workload, in the launch configuration the benchmark times:
+    total, a checksum of the whole per-vertex array and sampled per-vertex
+    counts against values stored by the oracle."""
+    exp = json.load(open(GOLDEN))["rmat22"]
+    g = W.large_rmat()
+    say(f"[gpu] rmat22 n={g.n} m_in={g.m_in}")
+    graph = ctx.build(g.src, g.dst, g.n)
+    info = graph.info()
+    assert (info.m, info.wedges_plus, info.max_dplus) == (exp["m"], exp["wedges_plus"], exp["max_dplus"])
+    tot, pv = graph.count(per_vertex=True)
+    assert tot == exp["total"]
+    pvn = pv.cpu().numpy().astype(np.uint64)
+    x = np.arange(g.n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        chk = int(np.sum(pvn * (x * np.uint64(0x9E3779B97F4A7C15) + np.uint64(1)), dtype=np.uint64))
+    assert chk == exp["per_vertex_checksum"]
+    ids = np.array(exp["sample_ids"])
+    assert (pvn[ids] == np.array(exp["sample_counts"], dtype=np.uint64)).all()
+    assert int(pvn.sum()) == 3 * tot
+    # one-shot entry point agrees
+    assert ctx.count(g.src, g.dst, g.n)[0] == exp["total"]

@@ -223,19 +223,21 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_total, uint
     a.hub_words = L.hub_words;
     a.hub_wgs = L.hub_wgs;
     a.slice_words = slice_words(p);
+    a.table_words = p.wg_lds_bytes / 4;
     a.load_pct = p.load_factor_pct;
     a.chunk = p.light_chunk;
     const uint32_t threads = 64 * p.wg_waves;
+    const uint32_t lds_bytes = p.wg_lds_bytes + p.wg_waves * tc::kQueueBytes;
     int per_cu = 0;
-    HIP_TRY(ctx, tc::count_kernel_info(p.slots_per_bucket, pv, p.hash_kind, threads, p.wg_lds_bytes, &per_cu));
-    if (per_cu < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, p.wg_lds_bytes);
+    HIP_TRY(ctx, tc::count_kernel_info(p.slots_per_bucket, pv, p.hash_kind, threads, lds_bytes, &per_cu));
+    if (per_cu < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, lds_bytes);
     uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu * ctx->cu_count);
     if (grid < a.hub_wgs) a.hub_wgs = grid;
     HIP_TRY(ctx, tc::fill_u32(a.heads, 0, 4, s));
     HIP_TRY(ctx, tc::fill_u32(d_total, 0, 2, s));
     if (pv) HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * (size_t)g->n, s));
     if (ctx->timing) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
-    HIP_TRY(ctx, tc::count_launch(p.slots_per_bucket, pv, p.hash_kind, grid, threads, p.wg_lds_bytes, a, s));
+    HIP_TRY(ctx, tc::count_launch(p.slots_per_bucket, pv, p.hash_kind, grid, threads, lds_bytes, a, s));
     if (ctx->timing) {
         HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
         ctx->have_count = true;

@@ -70,40 +70,119 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Look w up in the table; on a hit, *slot gets its slot index.
+template <int S>
+struct Bucket {
+    uint32_t v[S];
+};
+
+template <int S>
+__device__ __forceinline__ Bucket<S> read_bucket(const uint32_t* slots, uint32_t b) {
+    Bucket<S> r;
+    if constexpr (S == 1) {
+        r.v[0] = slots[b];
+    } else if constexpr (S == 2) {
+        const u32x2 x = *reinterpret_cast<const u32x2*>(slots + 2 * b);
+        r.v[0] = x.x; r.v[1] = x.y;
+    } else {
+        const u32x4 x = *reinterpret_cast<const u32x4*>(slots + 4 * b);
+        r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
+    }
+    return r;
+}
+
+// One bucket step of a lookup: hit (slot index in *s), or "continue at the
+// next bucket" (bucket full and w not in it), or a miss (neither).
+template <int S>
+__device__ __forceinline__ void bucket_step(const Bucket<S>& v, uint32_t w, uint32_t b, bool act, bool* hit,
+                                            bool* cont, uint32_t* s) {
+    bool found = false;
+    uint32_t j0 = 0;
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j)
+        if (v.v[j] == w) { found = true; j0 = (uint32_t)j; }
+    *hit = act && found;
+    *cont = act && !found && v.v[S - 1] != kEmpty;
+    *s = b * S + j0;
+}
+
+// Full lookup by walking the chain lane by lane (used for global-memory tables).
 template <int S, int HK>
-__device__ __forceinline__ bool lookup(const uint32_t* slots, uint32_t w, uint32_t B, uint32_t* slot) {
+__device__ __forceinline__ bool lookup_chain(const uint32_t* slots, uint32_t w, uint32_t B, uint32_t* slot) {
     uint32_t b = hash_of<HK>(w, B);
     for (uint32_t t = 0; t < B; ++t) {
-        uint32_t v[S];
-        if constexpr (S == 1) {
-            v[0] = slots[b];
-        } else if constexpr (S == 2) {
-            const u32x2 x = *reinterpret_cast<const u32x2*>(slots + 2 * b);
-            v[0] = x.x; v[1] = x.y;
-        } else {
-            const u32x4 x = *reinterpret_cast<const u32x4*>(slots + 4 * b);
-            v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-        }
-        bool found = false;
-        uint32_t s = 0;
-#pragma unroll
-        for (int j = S - 1; j >= 0; --j)
-            if (v[j] == w) { found = true; s = b * S + j; }
-        if (found) { *slot = s; return true; }
-        if (v[S - 1] == kEmpty) return false;
+        const Bucket<S> v = read_bucket<S>(slots, b);
+        bool hit, cont;
+        bool act = true;
+        bucket_step<S>(v, w, b, act, &hit, &cont, slot);
+        if (hit) return true;
+        if (!cont) return false;
         b = (b + 1) & (B - 1);
     }
     return false;
 }
 
 constexpr int kUnroll = 4;
+constexpr uint32_t kQueueCap = kQueueBytes / 8;  // deferred lookups per wavefront (entries of two words)
+static_assert(kQueueCap >= 127, "a wavefront holds < 64 entries plus one chunk of 64 pushes");
+
+struct Probe {
+    const uint32_t* __restrict__ col;
+    const uint32_t* slots;
+    const u32x2* P;
+    const uint32_t* selem;
+    uint32_t* tally;
+    u32x2* q;        // per-wavefront stack of deferred lookups {w, next bucket << 16 | k} (LDS), or null
+    uint32_t B;
+};
+
+template <int S, bool PV>
+__device__ __forceinline__ void tally_hit(const Probe& pr, uint32_t s, uint32_t k) {
+    if constexpr (PV) {
+        atomicAdd(&pr.tally[pr.selem[s]], 1u);
+        atomicAdd(&pr.tally[k], 1u);
+    }
+}
+
+// Push the lanes in `cont` onto the wavefront's stack (wave-uniform qn).
+__device__ __forceinline__ void push_deferred(u32x2* q, uint32_t& qn, bool cont, uint32_t w, uint32_t nb,
+                                              uint32_t k) {
+    const unsigned long long m = __ballot(cont);
+    if (m) {
+        const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (cont) q[pos] = u32x2{w, (nb << 16) | k};
+        qn += (uint32_t)__popcll(m);
+    }
+}
+
+// Resolve deferred lookups 64 at a time until fewer than `keep` remain.
+template <int S, bool PV>
+__device__ __forceinline__ void drain(const Probe& pr, uint32_t& qn, uint32_t keep, int lane,
+                                      unsigned long long& hits) {
+    while (qn >= keep && qn > 0) {
+        wave_sync();
+        const uint32_t take = qn < 64 ? qn : 64;
+        const uint32_t base = qn - take;
+        const bool mine = (uint32_t)lane < take;
+        u32x2 e = u32x2{kEmpty, 0u};
+        if (mine) e = pr.q[base + lane];
+        qn = base;
+        const uint32_t w = e.x, b = e.y >> 16, k = e.y & 0xFFFFu;
+        const Bucket<S> v = read_bucket<S>(pr.slots, b);
+        bool hit, cont;
+        uint32_t s;
+        bucket_step<S>(v, w, b, mine, &hit, &cont, &s);
+        hits += (unsigned long long)__popcll(__ballot(hit));
+        if (hit) tally_hit<S, PV>(pr, s, k);
+        wave_sync();
+        push_deferred(pr.q, qn, cont, w, (b + 1) & (pr.B - 1), k);
+    }
+}
 
 // Probe the flattened 2-hop range [lo, hi) of the current vertex with one wavefront.
-template <int S, bool PV, int HK>
-__device__ __forceinline__ unsigned long long probe_range(const uint32_t* __restrict__ col, const uint32_t* slots,
-                                                          const u32x2* P, const uint32_t* selem, uint32_t* tally,
-                                                          uint32_t B, uint32_t d, uint32_t lo, uint32_t hi,
+// Loads for the next group of kUnroll chunks are issued before the current group is probed.
+template <int S, bool PV, int HK, bool DEFER>
+__device__ __forceinline__ unsigned long long probe_range(const Probe& pr, uint32_t d, uint32_t lo, uint32_t hi,
                                                           int lane) {
     unsigned long long hits = 0;
     if (lo >= hi) return 0;
@@ -113,55 +192,91 @@ __device__ __forceinline__ unsigned long long probe_range(const uint32_t* __rest
         uint32_t l = 0, r = d - 1;
         while (l < r) {
             const uint32_t mid = (l + r) >> 1;
-            if (P[mid].x > i) r = mid; else l = mid + 1;
+            if (pr.P[mid].x > i) r = mid; else l = mid + 1;
         }
         k = l;
-        const u32x2 rec = P[k];
+        const u32x2 rec = pr.P[k];
         end = rec.x;
         base = rec.y;
     }
-    const uint32_t nch = (hi - lo + 63) >> 6;
-    for (uint32_t c = 0; c < nch; c += kUnroll) {
-        uint32_t w[kUnroll], kk[kUnroll];
-        bool act[kUnroll];
+    uint32_t qn = 0;
+
+    uint32_t wa[kUnroll], ka[kUnroll];
+    auto fetch = [&](uint32_t (&w)[kUnroll], uint32_t (&kk)[kUnroll]) {
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
             const uint32_t ii = i + 64u * j;
-            act[j] = ii < hi;
             w[j] = kEmpty;
             kk[j] = 0;
-            if (act[j]) {
+            if (ii < hi) {
                 while (ii >= end) {
                     ++k;
-                    const u32x2 rec = P[k];
+                    const u32x2 rec = pr.P[k];
                     end = rec.x;
                     base = rec.y;
                 }
-                w[j] = col[(uint32_t)(base + ii)];
+                w[j] = pr.col[(uint32_t)(base + ii)];
                 kk[j] = k;
             }
         }
+        i += 64u * kUnroll;
+    };
+    auto probe_group = [&](const uint32_t (&w)[kUnroll], const uint32_t (&kk)[kUnroll], uint32_t i0) {
+        if constexpr (DEFER) {
+            // All bucket reads of the group first, then resolve them in order.
+            uint32_t b[kUnroll];
+            Bucket<S> v[kUnroll];
 #pragma unroll
-        for (int j = 0; j < kUnroll; ++j) {
-            uint32_t s = 0;
-            const bool hit = act[j] && lookup<S, HK>(slots, w[j], B, &s);
-            hits += (unsigned long long)__popcll(__ballot(hit));
-            if constexpr (PV) {
-                if (hit) {
-                    atomicAdd(&tally[selem[s]], 1u);
-                    atomicAdd(&tally[kk[j]], 1u);
-                }
+            for (int j = 0; j < kUnroll; ++j) {
+                b[j] = hash_of<HK>(w[j], pr.B);
+                v[j] = read_bucket<S>(pr.slots, b[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) {
+                const bool act = i0 + 64u * j < hi;
+                bool hit, cont;
+                uint32_t s;
+                bucket_step<S>(v[j], w[j], b[j], act, &hit, &cont, &s);
+                hits += (unsigned long long)__popcll(__ballot(hit));
+                if (hit) tally_hit<S, PV>(pr, s, kk[j]);
+                push_deferred(pr.q, qn, cont, w[j], (b[j] + 1) & (pr.B - 1), kk[j]);
+                if (qn >= 64) drain<S, PV>(pr, qn, 64, lane, hits);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) {
+                const bool act = i0 + 64u * j < hi;
+                uint32_t s = 0;
+                const bool hit = act && lookup_chain<S, HK>(pr.slots, w[j], pr.B, &s);
+                hits += (unsigned long long)__popcll(__ballot(hit));
+                if (hit) tally_hit<S, PV>(pr, s, kk[j]);
             }
         }
-        i += 64u * kUnroll;
+    };
+
+    const uint32_t nch = (hi - lo + 63) >> 6;
+    uint32_t i0 = i;
+    fetch(wa, ka);
+    for (uint32_t c = 0; c < nch; c += kUnroll) {
+        uint32_t wb[kUnroll], kb[kUnroll];
+        const uint32_t i1 = i;
+        const bool more = c + kUnroll < nch;
+        if (more) fetch(wb, kb);
+        probe_group(wa, ka, i0);
+        if (more) {
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) { wa[j] = wb[j]; ka[j] = kb[j]; }
+        }
+        i0 = i1;
     }
+    if constexpr (DEFER) drain<S, PV>(pr, qn, 1, lane, hits);
     return hits;
 }
 
 // Process vertex u with a group of `gsz` lanes (one wavefront, or the workgroup when WG).
-template <int S, bool PV, int HK, bool WG>
-__device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t* tbl, int gl, int gsz, int gwave,
-                                        int gnw, int lane, uint32_t* s_wsum, unsigned long long& acc) {
+template <int S, bool PV, int HK, bool WG, bool DEFER>
+__device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t* tbl, u32x2* queue, int gl, int gsz,
+                                        int gwave, int gnw, int lane, uint32_t* s_wsum, unsigned long long& acc) {
     const int64_t beg = a.off[u];
     const uint32_t d = (uint32_t)(a.off[u + 1] - beg);
     const Geometry g = geometry(d, S, a.load_pct, PV);
@@ -227,7 +342,8 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
     const uint32_t W = carry;
     const uint32_t lo = (uint32_t)(((uint64_t)W * gwave) / gnw);
     const uint32_t hi = (uint32_t)(((uint64_t)W * (gwave + 1)) / gnw);
-    const unsigned long long hits = probe_range<S, PV, HK>(a.col, slots, P, selem, tally, g.B, d, lo, hi, lane);
+    const Probe pr{a.col, slots, P, selem, tally, queue, g.B};
+    const unsigned long long hits = probe_range<S, PV, HK, DEFER>(pr, d, lo, hi, lane);
     acc += hits;
 
     if constexpr (PV) {
@@ -250,6 +366,8 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     unsigned long long acc = 0;
     const uint32_t n_hub = a.meta->bins[0], n_wg = a.meta->bins[1], n_wave = a.meta->bins[2];
+    // Deferred-lookup stacks, one per wavefront, after the table area.
+    u32x2* queue = reinterpret_cast<u32x2*>(lds + a.table_words) + (size_t)wave * kQueueCap;
 
     // Hub bin: global-memory tables, one region per participating workgroup.
     if (blockIdx.x < a.hub_wgs && n_hub) {
@@ -260,7 +378,7 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_hub) break;
-            process<S, PV, HK, true>(a, a.items[j], gt, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
+            process<S, PV, HK, true, false>(a, a.items[j], gt, nullptr, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
         }
     }
     // Workgroup bin: the table fills the workgroup's LDS.
@@ -271,7 +389,8 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_wg) break;
-            process<S, PV, HK, true>(a, a.items[n_hub + j], lds, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
+            process<S, PV, HK, true, true>(a, a.items[n_hub + j], lds, queue, tid, blockDim.x, wave, nw, lane, s_wsum,
+                                           acc);
         }
     }
     // Wavefront bin: each wavefront owns a slice of the LDS.
@@ -285,7 +404,7 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
             if (j0 >= n_wave) break;
             const uint32_t j1 = (j0 + a.chunk < n_wave) ? j0 + a.chunk : n_wave;
             for (uint32_t j = j0; j < j1; ++j)
-                process<S, PV, HK, false>(a, a.items[base + j], slice, lane, 64, 0, 1, lane, nullptr, acc);
+                process<S, PV, HK, false, true>(a, a.items[base + j], slice, queue, lane, 64, 0, 1, lane, nullptr, acc);
         }
     }
 

@@ -12,6 +12,7 @@ namespace tc {
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash slot; never a valid id (ids < n <= 2^32 - 1)
 constexpr uint32_t kMaxWaves = 16;
 constexpr uint32_t kHubWgs = 128;        // workgroups that take global-memory-table vertices
+constexpr uint32_t kQueueBytes = 1024;   // LDS per wavefront for deferred lookups (128 entries of 8 bytes)
 
 // Device-resident summary of a built graph (first 256 bytes of its storage).
 struct GraphMeta {
@@ -117,6 +118,7 @@ struct CountArgs {
     unsigned long long hub_words;
     uint32_t hub_wgs;
     uint32_t slice_words;            // per-wavefront LDS slice
+    uint32_t table_words;            // LDS words for tables; the deferred-lookup stacks follow
     uint32_t load_pct;
     uint32_t chunk;
 };

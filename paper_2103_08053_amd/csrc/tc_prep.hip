@@ -71,13 +71,20 @@ __global__ void k_fix_m(const unsigned long long* keys, unsigned long long senti
     meta->m = u;
 }
 
+// Degrees from the sorted, unique keys.  The lower endpoint of a key is
+// constant over a run of consecutive keys, so its degree is the run length:
+// the run's first key subtracts its index and the run's last key adds its
+// index + 1 (one atomic each, mod 2^32), which avoids hammering one counter
+// per hub vertex.  The upper endpoint counts with one atomic per key.
 __global__ void k_degree(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
                          const GraphMeta* meta, uint32_t* __restrict__ deg) {
     const uint64_t m = meta->m;
     const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap && i < m; i += (uint64_t)gridDim.x * blockDim.x) {
         const unsigned long long k = keys[i];
-        atomicAdd(&deg[(uint32_t)(k >> nb)], 1u);
+        const uint32_t lo = (uint32_t)(k >> nb);
+        if (i == 0 || (uint32_t)(keys[i - 1] >> nb) != lo) atomicSub(&deg[lo], (uint32_t)i);
+        if (i + 1 == m || (uint32_t)(keys[i + 1] >> nb) != lo) atomicAdd(&deg[lo], (uint32_t)(i + 1));
         atomicAdd(&deg[(uint32_t)(k & mask)], 1u);
     }
 }

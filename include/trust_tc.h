@@ -148,6 +148,44 @@ tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out)
 /* Free the handle (host memory only; the storage stays the caller's). */
 tc_status tc_graph_release(tc_graph* g);
 
+/* ---------------------------------------------------------------- batches of graphs
+ * k graphs in one call.  Graph g has n_g vertices (local ids 0..n_g-1) and
+ * the edge samples [eoff[g], eoff[g+1]) of the concatenated arrays d_src /
+ * d_dst; voff[g] = n_0 + ... + n_{g-1} and voff[k] = n_total, eoff[k] =
+ * m_total (device uint64 arrays of k+1 entries, read during the build).
+ * The batch is cleaned, oriented and binned as one disjoint union (a
+ * disjoint union's triangles are the union of its parts' triangles), so one
+ * set of preprocessing launches and ONE persistent count launch serve all k
+ * graphs.  A local id >= n_g is a range error for the batch.
+ * Sizes: storage / temp as for one graph of n_total vertices and m_total
+ * samples plus 4 * n_total bytes (graph index of every vertex); see
+ * tc_batch_footprint. */
+tc_status tc_batch_footprint(const tc_context* ctx, uint32_t k, uint32_t n_total, uint64_t m_total,
+                             uint64_t* storage_bytes, uint64_t* temp_bytes);
+tc_status tc_batch_build(tc_context* ctx, uint32_t k, uint32_t n_total, uint64_t m_total,
+                         const uint64_t* d_voff, const uint64_t* d_eoff, const uint32_t* d_src,
+                         const uint32_t* d_dst, void* d_storage, uint64_t storage_bytes, void* d_temp,
+                         uint64_t temp_bytes, void* stream, tc_graph** out);
+
+/* Count a built graph or batch, one total per graph: d_totals is a device
+ * uint64[k] (k = 1 for tc_graph_build graphs).  d_per_vertex: NULL or device
+ * uint64[n_total], indexed by position in the concatenated vertex ranges.
+ * Asynchronous; scratch as for tc_graph_count (tc_count_scratch_bytes with
+ * n_total and m_total). */
+tc_status tc_graph_count_each(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex,
+                              void* d_scratch, uint64_t scratch_bytes, void* stream);
+
+/* As tc_graph_count_each, but the device work (the clears, the count
+ * kernel and the per-vertex gather) is captured once into a HIP graph on a
+ * stream owned by ctx and replayed on `stream` by later calls with the same
+ * arguments (re-captured when they change).  For callers that launch the
+ * same count repeatedly with minimal host overhead. */
+tc_status tc_graph_count_replay(tc_context* ctx, tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex,
+                                void* d_scratch, uint64_t scratch_bytes, void* stream);
+
+/* Number of graphs (k) of a built graph or batch. */
+tc_status tc_graph_k(const tc_graph* g, uint32_t* k);
+
 /* ---------------------------------------------------------------- timing
  * With timing on, every tc_count / tc_graph_build / tc_graph_count records
  * HIP events on its stream around its device steps (events owned by ctx).

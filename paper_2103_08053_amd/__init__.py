@@ -3,5 +3,5 @@
 The computation lives in the HIP library ``libtrust_tc.so`` (C ABI in
 ``include/trust_tc.h``); :mod:`.tc` is its ctypes binding.
 """
-from .tc import (Context, Graph, GraphInfo, Params, RangeError, TCError, count, default_context,  # noqa: F401
+from .tc import (Batch, Context, Graph, GraphInfo, Params, RangeError, TCError, count, default_context,  # noqa: F401
                  load_library)

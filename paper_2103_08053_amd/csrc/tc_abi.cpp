@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "tc_internal.h"
 
@@ -21,16 +22,28 @@ struct tc_context {
     bool timing = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // build start/end, count start/end
     bool have_build = false, have_count = false;
+    hipStream_t capture_stream = nullptr;  // for tc_graph_count_replay
+    struct Occ {
+        uint32_t S, pv, hk, threads, lds;
+        int per_cu;
+    };
+    std::vector<Occ> occ;  // resident workgroups per CU, by kernel variant and launch shape
 };
 
 struct tc_graph {
     tc_context* ctx = nullptr;
     uint32_t n = 0;
     uint64_t m_in = 0;
+    uint32_t k = 1;          // graphs in the batch (1 for a single graph)
+    bool batch = false;
     tc_params p{};           // knobs the bins were sized with
     tc::BinCaps caps{};
     tc::GraphDev dev{};
     bool empty = false;      // n == 0 or m_in == 0: nothing on the device
+    // captured count (tc_graph_count_replay)
+    hipGraph_t hg = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* key[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -101,7 +114,7 @@ uint32_t dplus_bound(uint32_t n, uint64_t m_in) {
     return (uint32_t)b;
 }
 
-Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_in) {
+Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_in, bool batch = false) {
     Layout L{};
     size_t o = 0;
     L.s_meta = o;  o = align_up(o + sizeof(tc::GraphMeta));
@@ -109,6 +122,7 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     L.s_col = o;   o = align_up(o + sizeof(uint32_t) * (size_t)m_in);
     L.s_rank = o;  o = align_up(o + sizeof(uint32_t) * (size_t)n);
     L.s_items = o; o = align_up(o + sizeof(uint32_t) * (size_t)n);
+    L.s_gid = o;   o = align_up(o + (batch ? sizeof(uint32_t) * (size_t)n : 0));
     L.storage = o;
 
     o = 0;
@@ -144,6 +158,7 @@ tc::GraphDev graph_ptrs(void* storage, const Layout& L) {
     g.col = reinterpret_cast<uint32_t*>(b + L.s_col);
     g.rank = reinterpret_cast<uint32_t*>(b + L.s_rank);
     g.items = reinterpret_cast<uint32_t*>(b + L.s_items);
+    g.gid = nullptr;
     return g;
 }
 
@@ -173,10 +188,13 @@ tc_status use_device(tc_context* ctx) {
 }
 
 tc_status build_into(tc_context* ctx, tc_graph* g, uint32_t n, uint64_t m_in, const uint32_t* src,
-                     const uint32_t* dst, void* storage, void* temp, const Layout& L, hipStream_t s) {
+                     const uint32_t* dst, void* storage, void* temp, const Layout& L, hipStream_t s,
+                     const tc::BatchIn* batch = nullptr) {
     g->ctx = ctx;
     g->n = n;
     g->m_in = m_in;
+    g->batch = batch != nullptr;
+    g->k = batch ? batch->k : 1;
     g->p = ctx->p;
     g->caps = bin_caps(ctx->p);
     g->empty = (n == 0 || m_in == 0);
@@ -191,9 +209,9 @@ tc_status build_into(tc_context* ctx, tc_graph* g, uint32_t n, uint64_t m_in, co
         return TC_OK;
     }
     g->dev = graph_ptrs(storage, L);
+    if (batch) g->dev.gid = reinterpret_cast<uint32_t*>(static_cast<char*>(storage) + L.s_gid);
     if (ctx->timing) HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
-    HIP_TRY(ctx, tc::prep_build(n, m_in, src, dst, g->dev, temp_ptrs(temp, L), g->caps, g->p.slots_per_bucket,
-                                g->p.load_factor_pct, s));
+    HIP_TRY(ctx, tc::prep_build(n, m_in, src, dst, g->dev, temp_ptrs(temp, L), g->caps, batch, s));
     if (ctx->timing) {
         HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
         ctx->have_build = true;
@@ -201,13 +219,31 @@ tc_status build_into(tc_context* ctx, tc_graph* g, uint32_t n, uint64_t m_in, co
     return TC_OK;
 }
 
-tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_total, uint64_t* d_per_vertex, void* scratch,
-                     const Layout& L, hipStream_t s) {
+tc_status occupancy(tc_context* ctx, const tc_params& p, bool pv, int* per_cu) {
+    const uint32_t threads = 64 * p.wg_waves;
+    for (const auto& o : ctx->occ)
+        if (o.S == p.slots_per_bucket && o.pv == (uint32_t)pv && o.hk == p.hash_kind && o.threads == threads &&
+            o.lds == p.wg_lds_bytes) {
+            *per_cu = o.per_cu;
+            return TC_OK;
+        }
+    int q = 0;
+    HIP_TRY(ctx, tc::count_kernel_info(p.slots_per_bucket, pv, p.hash_kind, threads, p.wg_lds_bytes, &q));
+    if (q < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, p.wg_lds_bytes);
+    ctx->occ.push_back({p.slots_per_bucket, (uint32_t)pv, p.hash_kind, threads, p.wg_lds_bytes, q});
+    *per_cu = q;
+    return TC_OK;
+}
+
+// The count: clears, the persistent kernel and (per-vertex mode) the gather.
+// d_totals has g->k entries.  With `record` false no timing events are recorded (stream capture).
+tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex, void* scratch,
+                     const Layout& L, hipStream_t s, bool record = true) {
     const tc_params& p = g->p;
     const bool pv = d_per_vertex != nullptr;
     char* b = static_cast<char*>(scratch);
     if (g->empty) {
-        HIP_TRY(ctx, tc::fill_u32(d_total, 0, 2, s));
+        HIP_TRY(ctx, tc::fill_u32(d_totals, 0, 2 * (size_t)g->k, s));
         if (pv) HIP_TRY(ctx, tc::fill_u32(d_per_vertex, 0, 2 * (size_t)g->n, s));
         return TC_OK;
     }
@@ -217,33 +253,40 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_total, uint
     a.col = g->dev.col;
     a.items = g->dev.items;
     a.heads = reinterpret_cast<uint32_t*>(b + L.c_heads);
-    a.total = reinterpret_cast<unsigned long long*>(d_total);
+    a.gid = g->dev.gid;
+    a.total = g->dev.gid ? nullptr : reinterpret_cast<unsigned long long*>(d_totals);
+    a.totals = g->dev.gid ? reinterpret_cast<unsigned long long*>(d_totals) : nullptr;
     a.tv = pv ? reinterpret_cast<unsigned long long*>(b + L.c_tv) : nullptr;
     a.hub_scratch = reinterpret_cast<uint32_t*>(b + L.c_hub);
     a.hub_words = L.hub_words;
     a.hub_wgs = L.hub_wgs;
     a.slice_words = slice_words(p);
-    a.table_words = p.wg_lds_bytes / 4;
     a.load_pct = p.load_factor_pct;
     a.chunk = p.light_chunk;
     const uint32_t threads = 64 * p.wg_waves;
-    const uint32_t lds_bytes = p.wg_lds_bytes + p.wg_waves * tc::kQueueBytes;
     int per_cu = 0;
-    HIP_TRY(ctx, tc::count_kernel_info(p.slots_per_bucket, pv, p.hash_kind, threads, lds_bytes, &per_cu));
-    if (per_cu < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, lds_bytes);
+    if (tc_status st = occupancy(ctx, p, pv, &per_cu)) return st;
     uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu * ctx->cu_count);
     if (grid < a.hub_wgs) a.hub_wgs = grid;
     HIP_TRY(ctx, tc::fill_u32(a.heads, 0, 4, s));
-    HIP_TRY(ctx, tc::fill_u32(d_total, 0, 2, s));
+    HIP_TRY(ctx, tc::fill_u32(d_totals, 0, 2 * (size_t)g->k, s));
     if (pv) HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * (size_t)g->n, s));
-    if (ctx->timing) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
-    HIP_TRY(ctx, tc::count_launch(p.slots_per_bucket, pv, p.hash_kind, grid, threads, lds_bytes, a, s));
-    if (ctx->timing) {
+    const bool rec = record && ctx->timing;
+    if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
+    HIP_TRY(ctx, tc::count_launch(p.slots_per_bucket, pv, p.hash_kind, grid, threads, p.wg_lds_bytes, a, s));
+    if (rec) {
         HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
         ctx->have_count = true;
     }
     if (pv) HIP_TRY(ctx, tc::gather_per_vertex(a.tv, g->dev.rank, g->n, reinterpret_cast<unsigned long long*>(d_per_vertex), s));
     return TC_OK;
+}
+
+void drop_capture(tc_graph* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->hg) (void)hipGraphDestroy(g->hg);
+    g->exec = nullptr;
+    g->hg = nullptr;
 }
 
 }  // namespace
@@ -307,6 +350,7 @@ tc_status tc_destroy(tc_context* ctx) {
     if (!ctx) return TC_OK;
     for (hipEvent_t& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
     return TC_OK;
 }
@@ -428,6 +472,7 @@ tc_status tc_graph_build(tc_context* ctx, uint32_t n, uint64_t m_in, const uint3
 tc_status tc_graph_count(tc_context* ctx, const tc_graph* g, uint64_t* d_total, uint64_t* d_per_vertex,
                          void* d_scratch, uint64_t scratch_bytes, void* stream) {
     if (!ctx || !g || !d_total) return TC_E_INVALID;
+    if (g->k != 1) return fail(ctx, TC_E_INVALID, "a batch of %u graphs needs tc_graph_count_each", g->k);
     ctx->err.clear();
     const Layout L = layout(ctx, g->p, g->n, g->m_in);
     if (!d_scratch || scratch_bytes < L.scratch) return fail(ctx, TC_E_NOMEM, "scratch too small");
@@ -458,7 +503,90 @@ tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out)
 }
 
 tc_status tc_graph_release(tc_graph* g) {
+    if (!g) return TC_OK;
+    drop_capture(g);
     delete g;
+    return TC_OK;
+}
+
+tc_status tc_graph_k(const tc_graph* g, uint32_t* k) {
+    if (!g || !k) return TC_E_INVALID;
+    *k = g->k;
+    return TC_OK;
+}
+
+tc_status tc_batch_footprint(const tc_context* ctx, uint32_t k, uint32_t n_total, uint64_t m_total,
+                             uint64_t* storage_bytes, uint64_t* temp_bytes) {
+    if (!ctx || !storage_bytes || !temp_bytes || k == 0) return TC_E_INVALID;
+    if (m_total >= (1ull << 31)) return TC_E_UNSUPPORTED;
+    const Layout L = layout(ctx, ctx->p, n_total, m_total, true);
+    *storage_bytes = L.storage;
+    *temp_bytes = L.temp;
+    return TC_OK;
+}
+
+tc_status tc_batch_build(tc_context* ctx, uint32_t k, uint32_t n_total, uint64_t m_total, const uint64_t* d_voff,
+                         const uint64_t* d_eoff, const uint32_t* d_src, const uint32_t* d_dst, void* d_storage,
+                         uint64_t storage_bytes, void* d_temp, uint64_t temp_bytes, void* stream, tc_graph** out) {
+    if (!ctx || !out) return TC_E_INVALID;
+    *out = nullptr;
+    ctx->err.clear();
+    if (k == 0 || !d_voff || !d_eoff) return fail(ctx, TC_E_INVALID, "a batch needs k >= 1 and offset arrays");
+    if (m_total && (!d_src || !d_dst)) return fail(ctx, TC_E_INVALID, "null edge arrays");
+    if (tc_status s = check_sizes(ctx, m_total)) return s;
+    const Layout L = layout(ctx, ctx->p, n_total, m_total, true);
+    if (!d_storage || storage_bytes < L.storage) return fail(ctx, TC_E_NOMEM, "storage too small");
+    if (L.temp && (!d_temp || temp_bytes < L.temp)) return fail(ctx, TC_E_NOMEM, "temp too small");
+    if (tc_status s = use_device(ctx)) return s;
+    tc_graph* g = new (std::nothrow) tc_graph();
+    if (!g) return TC_E_NOMEM;
+    const tc::BatchIn bi{reinterpret_cast<const unsigned long long*>(d_voff),
+                         reinterpret_cast<const unsigned long long*>(d_eoff), k};
+    tc_status s = build_into(ctx, g, n_total, m_total, d_src, d_dst, d_storage, d_temp, L,
+                             static_cast<hipStream_t>(stream), &bi);
+    if (s != TC_OK) { delete g; return s; }
+    *out = g;
+    return TC_OK;
+}
+
+tc_status tc_graph_count_each(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex,
+                              void* d_scratch, uint64_t scratch_bytes, void* stream) {
+    if (!ctx || !g || !d_totals) return TC_E_INVALID;
+    ctx->err.clear();
+    const Layout L = layout(ctx, g->p, g->n, g->m_in, g->batch);
+    if (!d_scratch || scratch_bytes < L.scratch) return fail(ctx, TC_E_NOMEM, "scratch too small");
+    if (tc_status s = use_device(ctx)) return s;
+    return count_into(ctx, g, d_totals, d_per_vertex, d_scratch, L, static_cast<hipStream_t>(stream));
+}
+
+tc_status tc_graph_count_replay(tc_context* ctx, tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex,
+                                void* d_scratch, uint64_t scratch_bytes, void* stream) {
+    if (!ctx || !g || !d_totals) return TC_E_INVALID;
+    ctx->err.clear();
+    const Layout L = layout(ctx, g->p, g->n, g->m_in, g->batch);
+    if (!d_scratch || scratch_bytes < L.scratch) return fail(ctx, TC_E_NOMEM, "scratch too small");
+    if (tc_status s = use_device(ctx)) return s;
+    const void* key[3] = {d_totals, d_per_vertex, d_scratch};
+    if (!g->exec || std::memcmp(key, g->key, sizeof(key)) != 0) {
+        drop_capture(g);
+        if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        int per_cu = 0;  // resolve launch shapes before capture (no attribute calls while capturing)
+        if (!g->empty)
+            if (tc_status st = occupancy(ctx, g->p, d_per_vertex != nullptr, &per_cu)) return st;
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        tc_status st = count_into(ctx, g, d_totals, d_per_vertex, d_scratch, L, ctx->capture_stream, false);
+        hipGraph_t hg = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->capture_stream, &hg);
+        if (st != TC_OK) {
+            if (hg) (void)hipGraphDestroy(hg);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+        g->hg = hg;
+        HIP_TRY(ctx, hipGraphInstantiate(&g->exec, g->hg, nullptr, nullptr, 0));
+        std::memcpy(g->key, key, sizeof(key));
+    }
+    HIP_TRY(ctx, hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
     return TC_OK;
 }
 

@@ -28,10 +28,15 @@
 //            (coalesced); each lane keeps a cursor (k, end, base) that only
 //            moves forward.  Each w is looked up in its bucket (Algorithm 1,
 //            intersection / linearSearch); a hit is one triangle (u, v_k, w).
-//   reduce : the wavefront's hit mask is counted with one ballot + popcount
-//            (a wave-wide reduction on the scalar unit), accumulated per
-//            wavefront, summed across the workgroup in LDS and added to the
-//            total with one atomic per workgroup at the end.
+//            A lookup that must continue to the next bucket is parked in
+//            registers and resumed with other parked lookups, so chains never
+//            stall a whole wavefront (LDS tables; the global-memory tables of
+//            the hub bin walk chains lane by lane).
+//   reduce : the hit compares are balloted and counted with a popcount on
+//            the scalar unit, accumulated per wavefront, summed across the
+//            workgroup in LDS and added to the total with one atomic per
+//            workgroup at the end.  For a batch of graphs each vertex's hits
+//            go to its graph's total instead.
 // Per-vertex mode adds, per hit, LDS tallies for the matched slot's element
 // (w) and for v_k; after the probe, u's hits and the non-zero tallies go to
 // the per-vertex array with one global atomic each.
@@ -90,6 +95,36 @@ __device__ __forceinline__ Bucket<S> read_bucket(const uint32_t* slots, uint32_t
     return r;
 }
 
+// Bucket contains w (bitwise OR of compares, so the lane mask stays a
+// compare result and a ballot of it is a plain scalar OR).
+template <int S>
+__device__ __forceinline__ bool bucket_has(const Bucket<S>& v, uint32_t w) {
+    bool f = v.v[0] == w;
+#pragma unroll
+    for (int j = 1; j < S; ++j) f = f | (v.v[j] == w);
+    return f;
+}
+
+// Lanes whose bucket contains their w, as a wave mask.  Each compare is
+// balloted on its own so the masks stay scalar (a ballot of an OR of
+// compares would be rebuilt through vector registers).
+template <int S>
+__device__ __forceinline__ unsigned long long ballot_has(const Bucket<S>& v, uint32_t w) {
+    unsigned long long m = __ballot(v.v[0] == w);
+#pragma unroll
+    for (int j = 1; j < S; ++j) m |= __ballot(v.v[j] == w);
+    return m;
+}
+
+// Index of w within a bucket that contains it.
+template <int S>
+__device__ __forceinline__ uint32_t bucket_pos(const Bucket<S>& v, uint32_t w) {
+    uint32_t j0 = S - 1;
+#pragma unroll
+    for (int j = S - 2; j >= 0; --j) j0 = (v.v[j] == w) ? (uint32_t)j : j0;
+    return j0;
+}
+
 // One bucket step of a lookup: hit (slot index in *s), or "continue at the
 // next bucket" (bucket full and w not in it), or a miss (neither).
 template <int S>
@@ -122,8 +157,6 @@ __device__ __forceinline__ bool lookup_chain(const uint32_t* slots, uint32_t w, 
 }
 
 constexpr int kUnroll = 4;
-constexpr uint32_t kQueueCap = kQueueBytes / 8;  // deferred lookups per wavefront (entries of two words)
-static_assert(kQueueCap >= 127, "a wavefront holds < 64 entries plus one chunk of 64 pushes");
 
 struct Probe {
     const uint32_t* __restrict__ col;
@@ -131,7 +164,6 @@ struct Probe {
     const u32x2* P;
     const uint32_t* selem;
     uint32_t* tally;
-    u32x2* q;        // per-wavefront stack of deferred lookups {w, next bucket << 16 | k} (LDS), or null
     uint32_t B;
 };
 
@@ -143,52 +175,164 @@ __device__ __forceinline__ void tally_hit(const Probe& pr, uint32_t s, uint32_t 
     }
 }
 
-// Push the lanes in `cont` onto the wavefront's stack (wave-uniform qn).
-__device__ __forceinline__ void push_deferred(u32x2* q, uint32_t& qn, bool cont, uint32_t w, uint32_t nb,
-                                              uint32_t k) {
-    const unsigned long long m = __ballot(cont);
-    if (m) {
-        const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (cont) q[pos] = u32x2{w, (nb << 16) | k};
-        qn += (uint32_t)__popcll(m);
+// Probe the flattened 2-hop range [lo, hi) of the current vertex with one
+// wavefront, walking it in chunks of 64 consecutive indices (consecutive
+// lanes read consecutive words of a list).  Each lane keeps its own cursor
+// (k, end, base), which only moves forward.
+//
+// A lookup whose bucket is full without a match must continue at the next
+// bucket.  Instead of walking that chain while the other 63 lanes wait, the
+// lane parks the lookup (w, next bucket, k) in two registers; parked lookups
+// take one bucket step together when 32 lanes hold one, when a lane that
+// holds one needs to park another, and at the end of the range.
+//
+// Loads for the next group of kUnroll chunks are issued before the current
+// group is probed (two register sets used in turn); the ragged last chunk
+// is probed on its own with a lane predicate.
+template <int S, bool PV, int HK>
+__device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, uint32_t d, uint32_t lo, uint32_t hi,
+                                                              int lane) {
+    if (lo >= hi) return 0;
+    const uint32_t bmask = pr.B - 1;
+    uint32_t hits = 0;  // wave-uniform; W < 2^32
+    uint32_t ii = lo + (uint32_t)lane;
+    uint32_t k, end, base;
+    {
+        const uint32_t key = ii < hi ? ii : hi - 1;
+        uint32_t l = 0, r = d - 1;
+        while (l < r) {
+            const uint32_t mid = (l + r) >> 1;
+            if (pr.P[mid].x > key) r = mid; else l = mid + 1;
+        }
+        k = l;
+        const u32x2 rec = pr.P[k];
+        end = rec.x;
+        base = rec.y;
     }
-}
+    // Parked lookups: word, (next bucket << 16) | k, and the mask of lanes holding one.
+    uint32_t pw = 0, pbk = 0;
+    unsigned long long pm = 0;
 
-// Resolve deferred lookups 64 at a time until fewer than `keep` remain.
-template <int S, bool PV>
-__device__ __forceinline__ void drain(const Probe& pr, uint32_t& qn, uint32_t keep, int lane,
-                                      unsigned long long& hits) {
-    while (qn >= keep && qn > 0) {
-        wave_sync();
-        const uint32_t take = qn < 64 ? qn : 64;
-        const uint32_t base = qn - take;
-        const bool mine = (uint32_t)lane < take;
-        u32x2 e = u32x2{kEmpty, 0u};
-        if (mine) e = pr.q[base + lane];
-        qn = base;
-        const uint32_t w = e.x, b = e.y >> 16, k = e.y & 0xFFFFu;
+    auto step_parked = [&]() {
+        const unsigned long long mine = pm;
+        const uint32_t b = pbk >> 16;
         const Bucket<S> v = read_bucket<S>(pr.slots, b);
-        bool hit, cont;
-        uint32_t s;
-        bucket_step<S>(v, w, b, mine, &hit, &cont, &s);
-        hits += (unsigned long long)__popcll(__ballot(hit));
-        if (hit) tally_hit<S, PV>(pr, s, k);
-        wave_sync();
-        push_deferred(pr.q, qn, cont, w, (b + 1) & (pr.B - 1), k);
+        const unsigned long long hm = ballot_has<S>(v, pw) & mine;
+        const unsigned long long cmask = __ballot(v.v[S - 1] != kEmpty) & mine & ~hm;
+        hits += (uint32_t)__popcll(hm);
+        if constexpr (PV) {
+            if ((hm >> lane) & 1ull) tally_hit<S, PV>(pr, b * S + bucket_pos<S>(v, pw), pbk & 0xFFFFu);
+        }
+        const bool cont = (cmask >> lane) & 1ull;
+        pbk = cont ? ((((b + 1) & bmask) << 16) | (pbk & 0xFFFFu)) : pbk;
+        pm = cmask;
+    };
+
+    // Resolve one bucket read; `act` limits it to lanes in range (ragged chunk).
+    auto resolve = [&](const Bucket<S>& v, uint32_t w, uint32_t b, uint32_t kk, unsigned long long actm) {
+        const unsigned long long hm = ballot_has<S>(v, w) & actm;
+        const unsigned long long cm = __ballot(v.v[S - 1] != kEmpty) & actm & ~hm;
+        hits += (uint32_t)__popcll(hm);
+        if constexpr (PV) {
+            if (bucket_has<S>(v, w) & ((actm >> lane) & 1ull))
+                tally_hit<S, PV>(pr, b * S + bucket_pos<S>(v, w), kk);
+        }
+        if (cm) {
+            while (cm & pm) step_parked();
+            const bool cont = !bucket_has<S>(v, w) & (v.v[S - 1] != kEmpty) & ((actm >> lane) & 1ull);
+            pw = cont ? w : pw;
+            pbk = cont ? ((((b + 1) & bmask) << 16) | kk) : pbk;
+            pm |= cm;
+            if ((uint32_t)__popcll(pm) >= 32u) step_parked();
+        }
+    };
+
+    // Full chunk: every lane active.
+    auto fetch = [&](uint32_t& w, uint32_t& kk) {
+        if (ii >= end) {
+            do {
+                ++k;
+                const u32x2 rec = pr.P[k];
+                end = rec.x;
+                base = rec.y;
+            } while (ii >= end);
+        }
+        w = pr.col[(uint32_t)(base + ii)];
+        kk = k;
+        ii += 64u;
+    };
+    auto probe_group = [&](const uint32_t (&w)[kUnroll], const uint32_t (&kk)[kUnroll], uint32_t n) {
+        uint32_t b[kUnroll];
+        Bucket<S> v[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            b[j] = hash_of<HK>(w[j], pr.B);
+            v[j] = read_bucket<S>(pr.slots, b[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j)
+            if ((uint32_t)j < n) resolve(v[j], w[j], b[j], kk[j], ~0ull);
+    };
+
+    const uint32_t nfull = (hi - lo) >> 6;
+    if (nfull) {
+        uint32_t wa[kUnroll], ka[kUnroll], wb[kUnroll], kb[kUnroll];
+        uint32_t c = 0;
+        uint32_t na = nfull < (uint32_t)kUnroll ? nfull : (uint32_t)kUnroll;
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            wa[j] = 0; ka[j] = 0; wb[j] = 0; kb[j] = 0;
+            if ((uint32_t)j < na) fetch(wa[j], ka[j]);
+        }
+        c = na;
+        for (;;) {
+            const uint32_t nb = nfull - c < (uint32_t)kUnroll ? nfull - c : (uint32_t)kUnroll;
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j)
+                if ((uint32_t)j < nb) fetch(wb[j], kb[j]);
+            probe_group(wa, ka, na);
+            c += nb;
+            if (nb == 0) break;
+            na = nfull - c < (uint32_t)kUnroll ? nfull - c : (uint32_t)kUnroll;
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j)
+                if ((uint32_t)j < na) fetch(wa[j], ka[j]);
+            probe_group(wb, kb, nb);
+            c += na;
+            if (na == 0) break;
+        }
     }
+    // Ragged last chunk: lanes past hi sit out.
+    if (ii - (uint32_t)lane < hi) {
+        const bool act = ii < hi;
+        uint32_t w = 0;
+        if (act) {
+            while (ii >= end) {
+                ++k;
+                const u32x2 rec = pr.P[k];
+                end = rec.x;
+                base = rec.y;
+            }
+            w = pr.col[(uint32_t)(base + ii)];
+        }
+        const uint32_t b = hash_of<HK>(w, pr.B);
+        const Bucket<S> v = read_bucket<S>(pr.slots, b);
+        resolve(v, w, b, k, __ballot(act));
+    }
+    while (pm) step_parked();
+    return hits;
 }
 
-// Probe the flattened 2-hop range [lo, hi) of the current vertex with one wavefront.
-// Loads for the next group of kUnroll chunks are issued before the current group is probed.
-template <int S, bool PV, int HK, bool DEFER>
-__device__ __forceinline__ unsigned long long probe_range(const Probe& pr, uint32_t d, uint32_t lo, uint32_t hi,
-                                                          int lane) {
+// The same walk with a per-lane cursor and lane-by-lane chain lookups, for
+// tables in global memory (hub bin).
+template <int S, bool PV, int HK>
+__device__ __forceinline__ unsigned long long probe_range_global(const Probe& pr, uint32_t d, uint32_t lo,
+                                                                 uint32_t hi, int lane) {
     unsigned long long hits = 0;
     if (lo >= hi) return 0;
     uint32_t i = lo + (uint32_t)lane;
     uint32_t k = 0, end = 0, base = 0;
-    if (i < hi) {  // first k with end[k] > i
+    if (i < hi) {
         uint32_t l = 0, r = d - 1;
         while (l < r) {
             const uint32_t mid = (l + r) >> 1;
@@ -199,86 +343,40 @@ __device__ __forceinline__ unsigned long long probe_range(const Probe& pr, uint3
         end = rec.x;
         base = rec.y;
     }
-    uint32_t qn = 0;
-
-    uint32_t wa[kUnroll], ka[kUnroll];
-    auto fetch = [&](uint32_t (&w)[kUnroll], uint32_t (&kk)[kUnroll]) {
-#pragma unroll
-        for (int j = 0; j < kUnroll; ++j) {
-            const uint32_t ii = i + 64u * j;
-            w[j] = kEmpty;
-            kk[j] = 0;
-            if (ii < hi) {
-                while (ii >= end) {
-                    ++k;
-                    const u32x2 rec = pr.P[k];
-                    end = rec.x;
-                    base = rec.y;
-                }
-                w[j] = pr.col[(uint32_t)(base + ii)];
-                kk[j] = k;
+    for (; i - (uint32_t)lane < hi; i += 64u) {
+        bool hit = false;
+        uint32_t s = 0;
+        if (i < hi) {
+            while (i >= end) {
+                ++k;
+                const u32x2 rec = pr.P[k];
+                end = rec.x;
+                base = rec.y;
             }
+            const uint32_t w = pr.col[(uint32_t)(base + i)];
+            hit = lookup_chain<S, HK>(pr.slots, w, pr.B, &s);
         }
-        i += 64u * kUnroll;
-    };
-    auto probe_group = [&](const uint32_t (&w)[kUnroll], const uint32_t (&kk)[kUnroll], uint32_t i0) {
-        if constexpr (DEFER) {
-            // All bucket reads of the group first, then resolve them in order.
-            uint32_t b[kUnroll];
-            Bucket<S> v[kUnroll];
-#pragma unroll
-            for (int j = 0; j < kUnroll; ++j) {
-                b[j] = hash_of<HK>(w[j], pr.B);
-                v[j] = read_bucket<S>(pr.slots, b[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < kUnroll; ++j) {
-                const bool act = i0 + 64u * j < hi;
-                bool hit, cont;
-                uint32_t s;
-                bucket_step<S>(v[j], w[j], b[j], act, &hit, &cont, &s);
-                hits += (unsigned long long)__popcll(__ballot(hit));
-                if (hit) tally_hit<S, PV>(pr, s, kk[j]);
-                push_deferred(pr.q, qn, cont, w[j], (b[j] + 1) & (pr.B - 1), kk[j]);
-                if (qn >= 64) drain<S, PV>(pr, qn, 64, lane, hits);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < kUnroll; ++j) {
-                const bool act = i0 + 64u * j < hi;
-                uint32_t s = 0;
-                const bool hit = act && lookup_chain<S, HK>(pr.slots, w[j], pr.B, &s);
-                hits += (unsigned long long)__popcll(__ballot(hit));
-                if (hit) tally_hit<S, PV>(pr, s, kk[j]);
-            }
-        }
-    };
-
-    const uint32_t nch = (hi - lo + 63) >> 6;
-    uint32_t i0 = i;
-    fetch(wa, ka);
-    for (uint32_t c = 0; c < nch; c += kUnroll) {
-        uint32_t wb[kUnroll], kb[kUnroll];
-        const uint32_t i1 = i;
-        const bool more = c + kUnroll < nch;
-        if (more) fetch(wb, kb);
-        probe_group(wa, ka, i0);
-        if (more) {
-#pragma unroll
-            for (int j = 0; j < kUnroll; ++j) { wa[j] = wb[j]; ka[j] = kb[j]; }
-        }
-        i0 = i1;
+        hits += (unsigned long long)__popcll(__ballot(hit));
+        if (hit) tally_hit<S, PV>(pr, s, k);
     }
-    if constexpr (DEFER) drain<S, PV>(pr, qn, 1, lane, hits);
     return hits;
+}
+
+template <int S, bool PV, int HK, bool DEFER>
+__device__ __forceinline__ unsigned long long probe_range(const Probe& pr, uint32_t d, uint32_t lo, uint32_t hi,
+                                                          int lane) {
+    if constexpr (DEFER) return probe_range_lds<S, PV, HK>(pr, d, lo, hi, lane);
+    else return probe_range_global<S, PV, HK>(pr, d, lo, hi, lane);
 }
 
 // Process vertex u with a group of `gsz` lanes (one wavefront, or the workgroup when WG).
 template <int S, bool PV, int HK, bool WG, bool DEFER>
-__device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t* tbl, u32x2* queue, int gl, int gsz,
+__device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t* tbl, int gl, int gsz,
                                         int gwave, int gnw, int lane, uint32_t* s_wsum, unsigned long long& acc) {
+    u = __builtin_amdgcn_readfirstlane(u);
+    gwave = __builtin_amdgcn_readfirstlane(gwave);
     const int64_t beg = a.off[u];
-    const uint32_t d = (uint32_t)(a.off[u + 1] - beg);
+    const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(a.off[u + 1] - beg));
     const Geometry g = geometry(d, S, a.load_pct, PV);
     uint32_t* slots = tbl;
     uint32_t* len = tbl + g.o_len;
@@ -339,12 +437,16 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
     group_sync<WG>();
 
     // Probe: the group's wavefronts split [0, W) into contiguous ranges.
-    const uint32_t W = carry;
-    const uint32_t lo = (uint32_t)(((uint64_t)W * gwave) / gnw);
-    const uint32_t hi = (uint32_t)(((uint64_t)W * (gwave + 1)) / gnw);
-    const Probe pr{a.col, slots, P, selem, tally, queue, g.B};
+    const uint32_t W = __builtin_amdgcn_readfirstlane(carry);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * gwave) / gnw));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * (gwave + 1)) / gnw));
+    const Probe pr{a.col, slots, P, selem, tally, g.B};
     const unsigned long long hits = probe_range<S, PV, HK, DEFER>(pr, d, lo, hi, lane);
-    acc += hits;
+    if (a.gid) {
+        if (lane == 0 && hits) atomicAdd(&a.totals[a.gid[u]], hits);
+    } else {
+        acc += hits;
+    }
 
     if constexpr (PV) {
         if (lane == 0 && hits) atomicAdd(&a.tv[u], hits);
@@ -366,8 +468,6 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     unsigned long long acc = 0;
     const uint32_t n_hub = a.meta->bins[0], n_wg = a.meta->bins[1], n_wave = a.meta->bins[2];
-    // Deferred-lookup stacks, one per wavefront, after the table area.
-    u32x2* queue = reinterpret_cast<u32x2*>(lds + a.table_words) + (size_t)wave * kQueueCap;
 
     // Hub bin: global-memory tables, one region per participating workgroup.
     if (blockIdx.x < a.hub_wgs && n_hub) {
@@ -378,7 +478,7 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_hub) break;
-            process<S, PV, HK, true, false>(a, a.items[j], gt, nullptr, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
+            process<S, PV, HK, true, false>(a, a.items[j], gt, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
         }
     }
     // Workgroup bin: the table fills the workgroup's LDS.
@@ -389,7 +489,7 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_wg) break;
-            process<S, PV, HK, true, true>(a, a.items[n_hub + j], lds, queue, tid, blockDim.x, wave, nw, lane, s_wsum,
+            process<S, PV, HK, true, true>(a, a.items[n_hub + j], lds, tid, blockDim.x, wave, nw, lane, s_wsum,
                                            acc);
         }
     }
@@ -404,7 +504,7 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
             if (j0 >= n_wave) break;
             const uint32_t j1 = (j0 + a.chunk < n_wave) ? j0 + a.chunk : n_wave;
             for (uint32_t j = j0; j < j1; ++j)
-                process<S, PV, HK, false, true>(a, a.items[base + j], slice, queue, lane, 64, 0, 1, lane, nullptr, acc);
+                process<S, PV, HK, false, true>(a, a.items[base + j], slice, lane, 64, 0, 1, lane, nullptr, acc);
         }
     }
 
@@ -413,7 +513,7 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
     if (tid == 0) {
         unsigned long long sum = 0;
         for (int w = 0; w < nw; ++w) sum += s_acc[w];
-        if (sum) atomicAdd(a.total, sum);
+        if (sum && a.total) atomicAdd(a.total, sum);
     }
 }
 

@@ -12,7 +12,6 @@ namespace tc {
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash slot; never a valid id (ids < n <= 2^32 - 1)
 constexpr uint32_t kMaxWaves = 16;
 constexpr uint32_t kHubWgs = 128;        // workgroups that take global-memory-table vertices
-constexpr uint32_t kQueueBytes = 1024;   // LDS per wavefront for deferred lookups (128 entries of 8 bytes)
 
 // Device-resident summary of a built graph (first 256 bytes of its storage).
 struct GraphMeta {
@@ -74,6 +73,14 @@ struct GraphDev {
     uint32_t* col;      // [m_in] out-neighbour lists (first meta->m entries used)
     uint32_t* rank;     // [n] input id -> rank
     uint32_t* items;    // [n] scheduled vertices: hub bin, workgroup bin, wavefront bin, skipped
+    uint32_t* gid;      // [n] graph index of each rank (batches only, else null)
+};
+
+// Batch description for the build (device arrays of k + 1 offsets).
+struct BatchIn {
+    const unsigned long long* voff;
+    const unsigned long long* eoff;
+    uint32_t k;
 };
 
 struct BuildTemp {
@@ -96,7 +103,7 @@ struct BinCaps {
 struct Layout {
     size_t storage, temp, scratch;
     // storage offsets
-    size_t s_meta, s_off, s_col, s_rank, s_items;
+    size_t s_meta, s_off, s_col, s_rank, s_items, s_gid;
     // temp offsets
     size_t t_keys_a, t_keys_b, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_sort;
     size_t sort_tmp_bytes;
@@ -112,13 +119,14 @@ struct CountArgs {
     const uint32_t* col;
     const uint32_t* items;
     uint32_t* heads;                 // [4] queue heads (zeroed before launch)
-    unsigned long long* total;       // [1] (zeroed before launch)
+    unsigned long long* total;       // [1] (zeroed before launch); single-graph mode
+    const uint32_t* gid;             // [n] graph of each rank (batch mode), or null
+    unsigned long long* totals;      // [k] per-graph totals (batch mode, zeroed before launch)
     unsigned long long* tv;          // [n] per-vertex counts in rank space, or null
     uint32_t* hub_scratch;           // hub_wgs * hub_words words
     unsigned long long hub_words;
     uint32_t hub_wgs;
     uint32_t slice_words;            // per-wavefront LDS slice
-    uint32_t table_words;            // LDS words for tables; the deferred-lookup stacks follow
     uint32_t load_pct;
     uint32_t chunk;
 };
@@ -126,8 +134,8 @@ struct CountArgs {
 // tc_prep.hip
 size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in);
 hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint32_t* dst,
-                      const GraphDev& g, const BuildTemp& t, const BinCaps& caps, uint32_t S,
-                      uint32_t load_pct, hipStream_t stream);
+                      const GraphDev& g, const BuildTemp& t, const BinCaps& caps, const BatchIn* batch,
+                      hipStream_t stream);
 hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream);
 hipError_t gather_per_vertex(const unsigned long long* tv_rank, const uint32_t* rank, uint32_t n,
                              unsigned long long* out, hipStream_t stream);

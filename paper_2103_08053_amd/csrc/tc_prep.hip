@@ -64,6 +64,50 @@ __global__ void k_canon(const uint32_t* __restrict__ src, const uint32_t* __rest
     if (bad) atomicOr(&meta->err, 1u);
 }
 
+// Largest g in [0, k) with off[g] <= x (off is non-decreasing, off[0] = 0).
+__device__ __forceinline__ uint32_t owner(const unsigned long long* off, uint32_t k, unsigned long long x) {
+    uint32_t lo = 0, hi = k - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Batch form: sample e belongs to graph g with eoff[g] <= e < eoff[g+1]; its
+// local ids are shifted by voff[g].  Local ids >= n_g, and union ids >= n
+// (malformed offsets), are range errors.
+__global__ void k_canon_batch(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst, uint64_t m_in,
+                              uint32_t n, uint32_t nb, unsigned long long sentinel,
+                              const unsigned long long* __restrict__ voff, const unsigned long long* __restrict__ eoff,
+                              uint32_t k, unsigned long long* __restrict__ keys, GraphMeta* meta) {
+    uint32_t bad = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 &&
+        (voff[0] != 0 || eoff[0] != 0 || voff[k] != n || eoff[k] != m_in))
+        bad = 1;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < m_in; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t g = owner(eoff, k, i);
+        const unsigned long long v0 = voff[g], ng = voff[g + 1] - v0;
+        const unsigned long long a = (unsigned long long)src[i] + v0, b = (unsigned long long)dst[i] + v0;
+        unsigned long long key;
+        if (src[i] >= ng || dst[i] >= ng || a >= n || b >= n) { bad = 1; key = sentinel; }
+        else if (a == b) key = sentinel;
+        else {
+            const unsigned long long lo = a < b ? a : b, hi = a < b ? b : a;
+            key = (lo << nb) | hi;
+        }
+        keys[i] = key;
+    }
+    if (bad) atomicOr(&meta->err, 1u);
+}
+
+// Graph index of every vertex in rank space.
+__global__ void k_gid(const uint32_t* __restrict__ order, uint32_t n, const unsigned long long* __restrict__ voff,
+                      uint32_t k, uint32_t* __restrict__ gid) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        gid[r] = owner(voff, k, order[r]);
+}
+
 // m = number of distinct keys minus the sentinel (present at most once, last).
 __global__ void k_fix_m(const unsigned long long* keys, unsigned long long sentinel, GraphMeta* meta) {
     uint32_t u = meta->m_unique;
@@ -209,9 +253,7 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
 }
 
 hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint32_t* dst, const GraphDev& g,
-                      const BuildTemp& t, const BinCaps& caps, uint32_t S, uint32_t load_pct,
-                      hipStream_t stream) {
-    (void)S; (void)load_pct;
+                      const BuildTemp& t, const BinCaps& caps, const BatchIn* batch, hipStream_t stream) {
     const uint32_t nb = id_bits(n);
     const unsigned long long sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1);
     size_t tmp = t.sort_tmp_bytes;
@@ -221,8 +263,12 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     TC_TRY(fill_u32(t.dplus, 0, (size_t)n + 1, stream));
 
     // 1-2: canonical keys, sort, unique.
-    hipLaunchKernelGGL(k_canon, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, src, dst, m_in, n, nb, sentinel,
-                       t.keys_a, g.meta);
+    if (batch)
+        hipLaunchKernelGGL(k_canon_batch, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, src, dst, m_in, n, nb,
+                           sentinel, batch->voff, batch->eoff, batch->k, t.keys_a, g.meta);
+    else
+        hipLaunchKernelGGL(k_canon, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, src, dst, m_in, n, nb, sentinel,
+                           t.keys_a, g.meta);
     TC_TRY(hipGetLastError());
     tmp = t.sort_tmp_bytes;
     TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, t.keys_a, t.keys_b, (size_t)m_in, 0, 2 * nb, stream));
@@ -246,6 +292,11 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
                                      t.order, (size_t)n, 0, deg_bits, stream));
     hipLaunchKernelGGL(k_rank, dim3(grid_for(n)), dim3(kThreads), 0, stream, t.order, n, g.rank);
     TC_TRY(hipGetLastError());
+    if (batch) {
+        hipLaunchKernelGGL(k_gid, dim3(grid_for(n)), dim3(kThreads), 0, stream, t.order, n, batch->voff, batch->k,
+                           g.gid);
+        TC_TRY(hipGetLastError());
+    }
 
     // 4-5: orientation and CSR in rank space.
     hipLaunchKernelGGL(k_orient_count, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta,

@@ -21,7 +21,8 @@ EXPORTS = [
     "tc_default_params", "tc_create", "tc_destroy", "tc_set_params", "tc_get_params", "tc_status_str",
     "tc_last_error", "tc_workspace_bytes", "tc_count", "tc_graph_footprint", "tc_graph_build",
     "tc_count_scratch_bytes", "tc_graph_count", "tc_graph_info_get", "tc_graph_release",
-    "tc_timing_enable", "tc_timing_last",
+    "tc_timing_enable", "tc_timing_last", "tc_batch_footprint", "tc_batch_build", "tc_graph_count_each",
+    "tc_graph_count_replay", "tc_graph_k",
 ]
 
 
@@ -113,6 +114,11 @@ def load_library(path: str = LIB_PATH):
         "tc_graph_info_get": [vp, vp, ctypes.POINTER(_GraphInfo)],
         "tc_graph_release": [vp],
         "tc_timing_enable": [vp, i32],
+        "tc_batch_footprint": [vp, u32, u32, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
+        "tc_batch_build": [vp, u32, u32, u64, vp, vp, vp, vp, vp, u64, vp, u64, vp, ctypes.POINTER(vp)],
+        "tc_graph_count_each": [vp, vp, vp, vp, vp, u64, vp],
+        "tc_graph_count_replay": [vp, vp, vp, vp, vp, u64, vp],
+        "tc_graph_k": [vp, ctypes.POINTER(u32)],
         "tc_timing_last": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
     }
     for name, args in sig.items():
@@ -218,6 +224,11 @@ class Context:
         _check(self.lib.tc_graph_footprint(self.h, n, m_in, ctypes.byref(s), ctypes.byref(t)), self.h)
         return s.value, t.value
 
+    def batch_footprint(self, k: int, n_total: int, m_total: int) -> tuple[int, int]:
+        s, t = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.tc_batch_footprint(self.h, k, n_total, m_total, ctypes.byref(s), ctypes.byref(t)), self.h)
+        return s.value, t.value
+
     def scratch_bytes(self, n: int, m_in: int) -> int:
         b = ctypes.c_uint64()
         _check(self.lib.tc_count_scratch_bytes(self.h, n, m_in, ctypes.byref(b)), self.h)
@@ -250,9 +261,10 @@ class Context:
 
 
 class Graph:
-    """A graph cleaned, oriented and binned once on the device; count it many times."""
+    """A graph (or a batch of graphs) cleaned, oriented and binned once on the
+    device; count it many times.  Use :meth:`Context.build` or :class:`Batch`."""
 
-    def __init__(self, ctx: Context, src, dst, n: int, stream=None, storage=None, temp=None):
+    def __init__(self, ctx: Context, src, dst, n: int, stream=None, storage=None, temp=None, _batch=None):
         torch = _torch()
         self.ctx = ctx
         self.n = n
@@ -260,17 +272,30 @@ class Graph:
         s = _edge_tensor(src, dev)
         d = _edge_tensor(dst, dev)
         self.m_in = s.numel()
-        sb, tb = ctx.footprint(n, self.m_in)
+        if _batch is None:
+            sb, tb = ctx.footprint(n, self.m_in)
+        else:
+            sb, tb = ctx.batch_footprint(_batch[0], n, self.m_in)
         self.storage = storage if storage is not None else torch.empty(max(sb, 1), dtype=torch.uint8, device=dev)
         tmp = temp if temp is not None else torch.empty(max(tb, 1), dtype=torch.uint8, device=dev)
         self.scratch = torch.empty(max(ctx.scratch_bytes(n, self.m_in), 1), dtype=torch.uint8, device=dev)
-        self.total_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         h = ctypes.c_void_p()
-        _check(ctx.lib.tc_graph_build(ctx.h, n, self.m_in, _ptr(s), _ptr(d), _ptr(self.storage),
-                                      self.storage.numel(), _ptr(tmp), tmp.numel(), _stream_ptr(stream),
-                                      ctypes.byref(h)), ctx.h)
+        if _batch is None:
+            _check(ctx.lib.tc_graph_build(ctx.h, n, self.m_in, _ptr(s), _ptr(d), _ptr(self.storage),
+                                          self.storage.numel(), _ptr(tmp), tmp.numel(), _stream_ptr(stream),
+                                          ctypes.byref(h)), ctx.h)
+        else:
+            k, voff, eoff = _batch
+            _check(ctx.lib.tc_batch_build(ctx.h, k, n, self.m_in, _ptr(voff), _ptr(eoff), _ptr(s), _ptr(d),
+                                          _ptr(self.storage), self.storage.numel(), _ptr(tmp), tmp.numel(),
+                                          _stream_ptr(stream), ctypes.byref(h)), ctx.h)
         self.h = h
-        self._keep = (s, d, tmp)  # alive until the build has run on the stream
+        kk = ctypes.c_uint32()
+        _check(ctx.lib.tc_graph_k(self.h, ctypes.byref(kk)))
+        self.k = kk.value
+        self.totals_dev = torch.zeros(self.k, dtype=torch.int64, device=dev)
+        self.total_dev = self.totals_dev[:1]
+        self._keep = (s, d, tmp, _batch)  # alive until the build has run on the stream
         self.info(stream)  # synchronises; raises RangeError on bad ids
         self._keep = None
 
@@ -279,18 +304,20 @@ class Graph:
         _check(self.ctx.lib.tc_graph_info_get(self.h, _stream_ptr(stream), ctypes.byref(gi)), self.ctx.h)
         return GraphInfo(**{k: int(getattr(gi, k)) for k, _ in _GraphInfo._fields_})
 
-    def count_async(self, per_vertex_out=None, stream=None):
-        """Launch the count; the total lands in ``self.total_dev`` (device int64)."""
-        _check(self.ctx.lib.tc_graph_count(self.ctx.h, self.h, _ptr(self.total_dev), _ptr(per_vertex_out),
-                                           _ptr(self.scratch), self.scratch.numel(), _stream_ptr(stream)),
-               self.ctx.h)
+    def count_async(self, per_vertex_out=None, stream=None, replay: bool = False):
+        """Launch the count; totals land in ``self.totals_dev`` (device int64[k]).
+        With ``replay`` the device work is captured once into a HIP graph and replayed."""
+        fn = self.ctx.lib.tc_graph_count_replay if replay else self.ctx.lib.tc_graph_count_each
+        _check(fn(self.ctx.h, self.h, _ptr(self.totals_dev), _ptr(per_vertex_out), _ptr(self.scratch),
+                  self.scratch.numel(), _stream_ptr(stream)), self.ctx.h)
 
-    def count(self, per_vertex: bool = False, stream=None):
+    def count(self, per_vertex: bool = False, stream=None, replay: bool = False):
+        """(total, per-vertex tensor or None) for a single graph; (totals list, ...) for a batch."""
         torch = _torch()
         pv = torch.empty(max(self.n, 1), dtype=torch.int64, device=self.storage.device) if per_vertex else None
-        self.count_async(pv, stream)
-        tot = int(self.total_dev.item())
-        return tot, (pv[: self.n] if per_vertex else None)
+        self.count_async(pv, stream, replay=replay)
+        tot = self.totals_dev.cpu().tolist()
+        return (tot[0] if self.k == 1 else tot), (pv[: self.n] if per_vertex else None)
 
     def release(self):
         if getattr(self, "h", None):
@@ -302,6 +329,30 @@ class Graph:
             self.release()
         except Exception:
             pass
+
+
+class Batch(Graph):
+    """k graphs counted together: one build and one persistent count launch.
+
+    ``graphs`` is a list of (n_g, src_g, dst_g) with local ids in [0, n_g)."""
+
+    def __init__(self, ctx: Context, graphs, stream=None):
+        import numpy as np
+        torch = _torch()
+        ns = np.array([int(g[0]) for g in graphs], dtype=np.int64)
+        ms = np.array([len(g[1]) for g in graphs], dtype=np.int64)
+        voff = np.zeros(len(graphs) + 1, np.int64)
+        eoff = np.zeros(len(graphs) + 1, np.int64)
+        np.cumsum(ns, out=voff[1:])
+        np.cumsum(ms, out=eoff[1:])
+        src = np.concatenate([np.asarray(g[1], dtype=np.uint32) for g in graphs]) if graphs else np.zeros(0, np.uint32)
+        dst = np.concatenate([np.asarray(g[2], dtype=np.uint32) for g in graphs]) if graphs else np.zeros(0, np.uint32)
+        dev = torch.device("cuda", ctx.device)
+        self.voff = voff
+        vo = torch.from_numpy(voff).to(dev)
+        eo = torch.from_numpy(eoff).to(dev)
+        super().__init__(ctx, src.view(np.int32), dst.view(np.int32), int(voff[-1]), stream=stream,
+                         _batch=(len(graphs), vo, eo))
 
 
 _default_ctx = None

@@ -63,6 +63,137 @@ def cpu_baseline(g, info, stride: int):
     }
 
 
+def run_batch(args):
+    """Batch of small graphs: one union build + one persistent count launch per
+    step (graphs/s), against a loop of per-graph plain tc_count calls."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import graphgen.workloads as W
+    from paper_2103_08053_amd import Batch, Context, Params
+    from paper_2103_08053_amd.tc import _check, _ptr, _stream_ptr
+
+    t0 = time.time()
+    specs = W.batch_spec(args.batch_graphs, seed=1)
+    graphs = [W.batch_graph(sp) for sp in specs]
+    log(f"[bench] generated {len(graphs)} graphs in {time.time() - t0:.1f}s")
+    params = Params()
+    tuned = None
+    if args.tune:
+        from paper_2103_08053_amd import autotune
+        sample = graphs[: max(64, len(graphs) // 8)]
+        params, tuned = autotune.tune([(g.n, g.src, g.dst) for g in sample], batch=True, use_cache=False,
+                                      trials=3, passes=1)
+        log(f"[bench] tuned: {tuned}")
+    ctx = Context(0, params)
+    dev = torch.device("cuda", 0)
+    # inputs resident in HBM: concatenated local-id edge lists + offsets
+    b0 = Batch(ctx, [(g.n, g.src, g.dst) for g in graphs])
+    n_tot, m_tot = b0.n, b0.m_in
+    src = torch.from_numpy(np.concatenate([g.src for g in graphs]).view(np.int32)).to(dev)
+    dst = torch.from_numpy(np.concatenate([g.dst for g in graphs]).view(np.int32)).to(dev)
+    voff = torch.from_numpy(b0.voff).to(dev)
+    eoff = torch.from_numpy(np.concatenate([[0], np.cumsum([g.m_in for g in graphs])]).astype(np.int64)).to(dev)
+    sb, tb = ctx.batch_footprint(len(graphs), n_tot, m_tot)
+    storage = torch.empty(sb, dtype=torch.uint8, device=dev)
+    temp = torch.empty(tb, dtype=torch.uint8, device=dev)
+    scratch = torch.empty(ctx.scratch_bytes(n_tot, m_tot), dtype=torch.uint8, device=dev)
+    totals = torch.empty(len(graphs), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    ref = torch.tensor(b0.count()[0], dtype=torch.int64, device=dev)
+    b0.release()
+
+    def step():
+        h = ctypes.c_void_p()
+        _check(ctx.lib.tc_batch_build(ctx.h, len(graphs), n_tot, m_tot, _ptr(voff), _ptr(eoff), _ptr(src), _ptr(dst),
+                                      _ptr(storage), sb, _ptr(temp), tb, _stream_ptr(stream), ctypes.byref(h)), ctx.h)
+        _check(ctx.lib.tc_graph_count_each(ctx.h, h, _ptr(totals), None, _ptr(scratch), scratch.numel(),
+                                           _stream_ptr(stream)), ctx.h)
+        return h
+
+    for _ in range(args.warmup):
+        ctx.lib.tc_graph_release(step())
+    torch.cuda.synchronize()
+    hs = []
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        hs.append(step())
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t) / args.steps
+    for h in hs:
+        ctx.lib.tc_graph_release(h)
+    assert torch.equal(totals, ref)
+    # per-graph plain path on a sample, scaled (each call: build + count + readback)
+    sample = graphs[:: max(1, len(graphs) // args.plain_sample)]
+    dsrc = [torch.from_numpy(g.src.view(np.int32)).to(dev) for g in sample]
+    ddst = [torch.from_numpy(g.dst.view(np.int32)).to(dev) for g in sample]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain = [ctx.count(s_, d_, g.n)[0] for s_, d_, g in zip(dsrc, ddst, sample)]
+    plain_s = (time.perf_counter() - t) * len(graphs) / len(sample)
+    refl = ref.cpu().tolist()
+    idx = list(range(0, len(graphs), max(1, len(graphs) // args.plain_sample)))
+    assert all(plain[i] == refl[j] for i, j in enumerate(idx))
+    out = {
+        "metric": "batched graphs/s (one build + one persistent count launch) vs per-graph plain launches",
+        "value": len(graphs) / batch_s, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": batch_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{len(graphs)} graphs: even ER (M = n k), odd BA (k in 4..16), n log-uniform "
+                               f"[100, 50000], SplitMix64 seeds", "n_total": n_tot, "m_total": m_tot,
+                   "params": vars(params), "tuned": tuned},
+        "plain_graphs_per_s": len(graphs) / plain_s,
+        "speedup_vs_plain": plain_s / batch_s,
+        "batched_teps_input_edges": m_tot / batch_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Poisson request stream over a pinned-host pool; continuous batching vs FIFO plain path."""
+    import numpy as np
+    import torch
+
+    import graphgen.workloads as W
+    from paper_2103_08053_amd import Context, serve
+
+    t0 = time.time()
+    specs = W.serving_pool(args.pool, seed=7, rmat_scales=(10, args.serve_max_scale))
+    pool = [W.serving_graph(sp) for sp in specs]
+    log(f"[bench] serving pool of {len(pool)} graphs in {time.time() - t0:.1f}s "
+        f"({sum(g.m_in for g in pool) / 1e6:.1f} M samples)")
+    arrivals = W.poisson_arrivals(args.rate, args.duration, seed=11)
+    ctx0 = Context(0)
+    alone = [ctx0.count(g.src, g.dst, g.n)[0] for g in pool]  # each graph counted on its own
+    res = {}
+    for mode in ("batched", "plain"):
+        reqs = [serve.make_request(i, pool[i % len(pool)].n, pool[i % len(pool)].src, pool[i % len(pool)].dst)
+                for i in range(len(arrivals))]
+        torch.cuda.synchronize()
+        if mode == "batched":
+            srv = serve.Server(0, hbm_budget=args.hbm_budget_gb << 30, max_batch=args.max_batch)
+            stats = srv.run(reqs, arrivals)
+        else:
+            stats = serve.serve_fifo(Context(0), reqs, arrivals)
+        res[mode] = stats
+        bad = [r.rid for r in reqs if r.total != alone[r.rid % len(pool)]]
+        assert not bad, f"{mode}: {len(bad)} requests differ from the graph counted alone"
+        log(f"[bench] serve {mode}: {stats}")
+    out = {
+        "metric": "served requests: p50/p99 latency and throughput, continuous batching vs plain FIFO",
+        "value": res["batched"]["throughput_rps"], "unit": "requests/s", "n_gpus": 1, "steps": len(arrivals),
+        "warmup": 0, "ms_per_step": 1e3 / max(res["batched"]["throughput_rps"], 1e-9), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"Poisson {args.rate}/s for {args.duration}s over {len(pool)} graphs (R-MAT scale "
+                               f"10-{args.serve_max_scale} ef 16, BA n 1e3-1e6 k 4-16)",
+                   "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch},
+        "batched": res["batched"], "plain": res["plain"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,11 +203,24 @@ def main():
     ap.add_argument("--no-per-vertex", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--plain-sample", type=int, default=256)
+    ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--pool", type=int, default=48)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--duration", type=float, default=2.0)
+    ap.add_argument("--serve-max-scale", type=int, default=20)
+    ap.add_argument("--hbm-budget-gb", type=int, default=96)
+    ap.add_argument("--max-batch", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design "
               f"note, not a built component", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
 
     import numpy as np
     import torch

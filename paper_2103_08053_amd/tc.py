@@ -264,7 +264,8 @@ class Graph:
     """A graph (or a batch of graphs) cleaned, oriented and binned once on the
     device; count it many times.  Use :meth:`Context.build` or :class:`Batch`."""
 
-    def __init__(self, ctx: Context, src, dst, n: int, stream=None, storage=None, temp=None, _batch=None):
+    def __init__(self, ctx: Context, src, dst, n: int, stream=None, storage=None, temp=None, _batch=None,
+                 sync: bool = True):
         torch = _torch()
         self.ctx = ctx
         self.n = n
@@ -296,8 +297,9 @@ class Graph:
         self.totals_dev = torch.zeros(self.k, dtype=torch.int64, device=dev)
         self.total_dev = self.totals_dev[:1]
         self._keep = (s, d, tmp, _batch)  # alive until the build has run on the stream
-        self.info(stream)  # synchronises; raises RangeError on bad ids
-        self._keep = None
+        if sync:
+            self.info(stream)  # synchronises; raises RangeError on bad ids
+            self._keep = None
 
     def info(self, stream=None) -> GraphInfo:
         gi = _GraphInfo()
@@ -334,25 +336,34 @@ class Graph:
 class Batch(Graph):
     """k graphs counted together: one build and one persistent count launch.
 
-    ``graphs`` is a list of (n_g, src_g, dst_g) with local ids in [0, n_g)."""
+    ``graphs`` is a list of (n_g, src_g, dst_g) with local ids in [0, n_g);
+    src_g / dst_g are host arrays or device tensors.  With ``sync=False`` the
+    build is only enqueued on ``stream`` (range errors then surface at the
+    next :meth:`info`)."""
 
-    def __init__(self, ctx: Context, graphs, stream=None):
+    def __init__(self, ctx: Context, graphs, stream=None, sync: bool = True):
         import numpy as np
         torch = _torch()
+        dev = torch.device("cuda", ctx.device)
         ns = np.array([int(g[0]) for g in graphs], dtype=np.int64)
         ms = np.array([len(g[1]) for g in graphs], dtype=np.int64)
         voff = np.zeros(len(graphs) + 1, np.int64)
         eoff = np.zeros(len(graphs) + 1, np.int64)
         np.cumsum(ns, out=voff[1:])
         np.cumsum(ms, out=eoff[1:])
-        src = np.concatenate([np.asarray(g[1], dtype=np.uint32) for g in graphs]) if graphs else np.zeros(0, np.uint32)
-        dst = np.concatenate([np.asarray(g[2], dtype=np.uint32) for g in graphs]) if graphs else np.zeros(0, np.uint32)
-        dev = torch.device("cuda", ctx.device)
+        if graphs and all(isinstance(g[1], torch.Tensor) and g[1].is_cuda for g in graphs):
+            src = torch.cat([g[1].view(torch.int32) for g in graphs])
+            dst = torch.cat([g[2].view(torch.int32) for g in graphs])
+        else:
+            src = np.concatenate([np.asarray(g[1], dtype=np.uint32) for g in graphs]) if graphs \
+                else np.zeros(0, np.uint32)
+            dst = np.concatenate([np.asarray(g[2], dtype=np.uint32) for g in graphs]) if graphs \
+                else np.zeros(0, np.uint32)
+            src, dst = src.view(np.int32), dst.view(np.int32)
         self.voff = voff
-        vo = torch.from_numpy(voff).to(dev)
-        eo = torch.from_numpy(eoff).to(dev)
-        super().__init__(ctx, src.view(np.int32), dst.view(np.int32), int(voff[-1]), stream=stream,
-                         _batch=(len(graphs), vo, eo))
+        vo = torch.from_numpy(voff).to(dev, non_blocking=True)
+        eo = torch.from_numpy(eoff).to(dev, non_blocking=True)
+        super().__init__(ctx, src, dst, int(voff[-1]), stream=stream, _batch=(len(graphs), vo, eo), sync=sync)
 
 
 _default_ctx = None

@@ -1,0 +1,57 @@
+"""Serving loop and autotuner on the GPU: results never change."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import graphgen.workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def test_served_results_equal_alone():
+    """Requests served in mixed, overlapping batches get exactly the count of
+    their graph counted alone."""
+    from paper_2103_08053_amd import Context, serve
+    pool = [gg.rmat(s, 16, seed=s) for s in (10, 12, 14)] + [gg.barabasi_albert(20000, k, seed=k) for k in (4, 9)] \
+        + [gg.complete(60), gg.torus3d(8)]
+    ctx = Context(0)
+    alone = [ctx.count(g.src, g.dst, g.n)[0] for g in pool]
+    arrivals = W.poisson_arrivals(400.0, 0.5, seed=3)
+    say(f"[gpu] serving {len(arrivals)} requests")
+    reqs = [serve.make_request(i, pool[i % len(pool)].n, pool[i % len(pool)].src, pool[i % len(pool)].dst)
+            for i in range(len(arrivals))]
+    srv = serve.Server(0, hbm_budget=2 << 30, max_batch=32)
+    stats = srv.run(reqs, arrivals)
+    say(f"[gpu] {stats}")
+    assert all(r.total == alone[r.rid % len(pool)] for r in reqs)
+    assert stats["batches"] >= 2 and all(r.done >= r.arrival for r in reqs)
+
+
+def test_fifo_baseline_results():
+    from paper_2103_08053_amd import Context, serve
+    pool = [gg.rmat(11, 16, seed=1), gg.complete(30)]
+    ctx = Context(0)
+    arrivals = np.linspace(0, 0.05, 10)
+    reqs = [serve.make_request(i, pool[i % 2].n, pool[i % 2].src, pool[i % 2].dst) for i in range(10)]
+    serve.serve_fifo(ctx, reqs, arrivals)
+    alone = [ctx.count(g.src, g.dst, g.n)[0] for g in pool]
+    assert all(r.total == alone[r.rid % 2] for r in reqs)
+
+
+def test_autotune_keeps_counts(tmp_path):
+    from paper_2103_08053_amd import Context, autotune
+    g = gg.rmat(13, 16, seed=7)
+    space = {"slots_per_bucket": [2, 4], "wg_lds_bytes": [32768, 65536], "light_chunk": [2, 8]}
+    p, rep = autotune.tune((g.src, g.dst, g.n), space=space, passes=1, trials=2,
+                           cache_path=str(tmp_path / "t.json"))
+    say(f"[gpu] tuned {rep}")
+    assert rep["evaluated"] >= 4
+    assert Context(0, p).count(g.src, g.dst, g.n)[0] == Context(0).count(g.src, g.dst, g.n)[0]
+    p2, rep2 = autotune.tune((g.src, g.dst, g.n), space=space, cache_path=str(tmp_path / "t.json"))
+    assert rep2["cached"] and p2 == p

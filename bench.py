@@ -49,6 +49,48 @@ def algorithmic_bytes(n: int, m: int, wplus: int, per_vertex: bool) -> int:
     return 8 * n + 4 * m + 16 * m + 4 * wplus + 8 + (8 * n if per_vertex else 0)
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_2103_08053_amd", "csrc", "tc_count.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "tc_count_kernel_rmat22_pmc.md")
+CALIB_BYTES = 1 << 30
+
+
+def kernel_source_sha1() -> str:
+    import hashlib
+    return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def measured_traffic(per_vertex: bool):
+    """DRAM-side bytes per count launch from the committed PMC summary, if it
+    was taken on the current kernel source and mode; else None."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    kv = {}
+    for line in open(PMC_SUMMARY):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel_source_sha1") != kernel_source_sha1():
+        return None
+    if kv.get("per_vertex", "").lower() != str(per_vertex).lower():
+        return None
+    try:
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size (read CALIB_BYTES, write
+    CALIB_BYTES), so FETCH_SIZE / WRITE_SIZE can be scaled to bytes."""
+    import torch
+    a = torch.empty(CALIB_BYTES, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def cpu_baseline(g, info, stride: int):
     import oracle
     r = oracle.count(g.n, g.src, g.dst, per_vertex=False, stride=stride)
@@ -203,6 +245,8 @@ def main():
     ap.add_argument("--no-per-vertex", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="run a 1 GiB device copy first (for scaling PMC byte counters)")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=256)
     ap.add_argument("--tune", action="store_true")
@@ -228,6 +272,8 @@ def main():
     from paper_2103_08053_amd import Context
 
     per_vertex = not args.no_per_vertex
+    if args.pmc_calibrate:
+        copy_calibration()
     t0 = time.time()
     g, desc = workload(args.workload)
     log(f"[bench] generated {args.workload}: n={g.n} m_in={g.m_in} in {time.time() - t0:.1f}s")
@@ -299,8 +345,9 @@ def main():
         "count_only_teps": info.m / (kernel_ms * 1e-3),
         "build_ms": float(np.mean(build_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "tc_count_kernel", "algorithmic_bytes": b_alg},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_vertex),
+                     "kernel": "tc_count_kernel", "algorithmic_bytes": b_alg,
+                     "kernel_source_sha1": kernel_source_sha1()},
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")

@@ -84,7 +84,8 @@ tc_status check_params(const tc_params* p) {
     if (p->load_factor_pct < 10 || p->load_factor_pct > 100) return TC_E_INVALID;
     if (p->hash_kind > 1) return TC_E_INVALID;
     if (p->light_chunk < 1 || p->light_chunk > 256) return TC_E_INVALID;
-    if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SORT_LISTS)) return TC_E_INVALID;
+    if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SORT_LISTS | TC_F_WIDE_ADDR))
+        return TC_E_INVALID;
     return TC_OK;
 }
 
@@ -261,8 +262,10 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.hub_words = L.hub_words;
     a.hub_wgs = L.hub_wgs;
     a.slice_words = slice_words(p);
+    a.table_words = p.wg_lds_bytes / 4;
     a.load_pct = p.load_factor_pct;
     a.chunk = p.light_chunk;
+    a.wide = (g->m_in >= (1ull << 30)) || (p.flags & TC_F_WIDE_ADDR) ? 1u : 0u;
     const uint32_t threads = 64 * p.wg_waves;
     int per_cu = 0;
     if (tc_status st = occupancy(ctx, p, pv, &per_cu)) return st;
@@ -313,12 +316,12 @@ tc_status tc_default_params(tc_params* p) {
     std::memset(p, 0, sizeof(*p));
     p->struct_size = sizeof(tc_params);
     p->wg_waves = 8;
-    p->wg_lds_bytes = 65536;
+    p->wg_lds_bytes = 49152;
     p->wave_max_dplus = 0;
-    p->slots_per_bucket = 2;
+    p->slots_per_bucket = 4;
     p->load_factor_pct = 50;
     p->hash_kind = 0;
-    p->light_chunk = 4;
+    p->light_chunk = 16;
     p->grid_wgs = 0;
     p->flags = 0;
     return TC_OK;

@@ -37,9 +37,9 @@
 //            workgroup in LDS and added to the total with one atomic per
 //            workgroup at the end.  For a batch of graphs each vertex's hits
 //            go to its graph's total instead.
-// Per-vertex mode adds, per hit, LDS tallies for the matched slot's element
-// (w) and for v_k; after the probe, u's hits and the non-zero tallies go to
-// the per-vertex array with one global atomic each.
+// Per-vertex mode adds, per hit, an LDS tally on the matched slot (its
+// element is the triangle's w) and one on v_k; after the probe, u's hits and
+// the non-zero tallies go to the per-vertex array with one global atomic each.
 #include "tc_internal.h"
 
 namespace tc {
@@ -162,43 +162,50 @@ struct Probe {
     const uint32_t* __restrict__ col;
     const uint32_t* slots;
     const u32x2* P;
-    const uint32_t* selem;
-    uint32_t* tally;
+    uint32_t* tslot;  // per-slot hit tallies (per-vertex mode): the slot's element is the triangle's w
+    uint32_t* tally;  // per-out-neighbour hit tallies (per-vertex mode): v_k of the triangle
     uint32_t B;
 };
 
 template <int S, bool PV>
 __device__ __forceinline__ void tally_hit(const Probe& pr, uint32_t s, uint32_t k) {
     if constexpr (PV) {
-        atomicAdd(&pr.tally[pr.selem[s]], 1u);
+        atomicAdd(&pr.tslot[s], 1u);
         atomicAdd(&pr.tally[k], 1u);
     }
 }
 
 // Probe the flattened 2-hop range [lo, hi) of the current vertex with one
 // wavefront, walking it in chunks of 64 consecutive indices (consecutive
-// lanes read consecutive words of a list).  Each lane keeps its own cursor
-// (k, end, base), which only moves forward.
+// lanes read consecutive words of a list).
+//
+// Each lane keeps a forward-only cursor as a position in col: `pos` (the
+// word it reads next) and `lim` (end of the current list).  A chunk step is
+// pos += 64; when pos passes lim the lane moves on to the next list(s) of the
+// virtual combination, carrying the overshoot.  With col under 4 GiB the
+// position is kept as a 32-bit byte offset and loads take the scalar-base
+// form (no 64-bit address arithmetic per chunk).
 //
 // A lookup whose bucket is full without a match must continue at the next
 // bucket.  Instead of walking that chain while the other 63 lanes wait, the
-// lane parks the lookup (w, next bucket, k) in two registers; parked lookups
-// take one bucket step together when 32 lanes hold one, when a lane that
-// holds one needs to park another, and at the end of the range.
+// lane parks it (w, bucket[, k]) in registers; parked lookups take one
+// bucket step together when 32 lanes hold one, when a lane that holds one
+// needs to park another, and at the end of the range.
 //
 // Loads for the next group of kUnroll chunks are issued before the current
-// group is probed (two register sets used in turn); the ragged last chunk
-// is probed on its own with a lane predicate.
-template <int S, bool PV, int HK>
+// group is probed (two register sets used in turn); leftover chunks are
+// probed one at a time and the ragged last chunk with a lane predicate.
+template <int S, bool PV, int HK, bool WIDE>
 __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, uint32_t d, uint32_t lo, uint32_t hi,
                                                               int lane) {
     if (lo >= hi) return 0;
     const uint32_t bmask = pr.B - 1;
     uint32_t hits = 0;  // wave-uniform; W < 2^32
-    uint32_t ii = lo + (uint32_t)lane;
-    uint32_t k, end, base;
+    // Cursor: record k holds the lane's next flattened index ii; pos = base_k + ii.
+    uint32_t k, pos, lim, base;
     {
-        const uint32_t key = ii < hi ? ii : hi - 1;
+        const uint32_t ii0 = lo + (uint32_t)lane;
+        const uint32_t key = ii0 < hi ? ii0 : hi - 1;
         uint32_t l = 0, r = d - 1;
         while (l < r) {
             const uint32_t mid = (l + r) >> 1;
@@ -206,29 +213,49 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         }
         k = l;
         const u32x2 rec = pr.P[k];
-        end = rec.x;
         base = rec.y;
+        pos = base + ii0;
+        lim = base + rec.x;
     }
-    // Parked lookups: word, (next bucket << 16) | k, and the mask of lanes holding one.
-    uint32_t pw = 0, pbk = 0;
+    // 32-bit byte offsets (narrow) or word indices with 64-bit addressing (wide).
+    const uint32_t step = WIDE ? 64u : 256u;
+    uint32_t cur = WIDE ? pos : pos * 4u, end = WIDE ? lim : lim * 4u;
+
+    auto advance = [&]() {  // cur >= end: move to the record holding the lane's index
+        const uint32_t ii = (WIDE ? cur : cur >> 2) - base;
+        uint32_t e;
+        do {
+            ++k;
+            const u32x2 rec = pr.P[k];
+            e = rec.x;
+            base = rec.y;
+        } while (ii >= e);
+        cur = WIDE ? base + ii : (base + ii) * 4u;
+        end = WIDE ? base + e : (base + e) * 4u;
+    };
+    auto load = [&]() -> uint32_t {
+        if constexpr (WIDE) return pr.col[cur];
+        else return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(pr.col) + cur);
+    };
+
+    // Parked lookups: word, bucket (and k in per-vertex mode), mask of lanes holding one.
+    uint32_t pw = 0, pb = 0, pk = 0;
     unsigned long long pm = 0;
 
     auto step_parked = [&]() {
         const unsigned long long mine = pm;
-        const uint32_t b = pbk >> 16;
+        const uint32_t b = (pb + 1) & bmask;
         const Bucket<S> v = read_bucket<S>(pr.slots, b);
         const unsigned long long hm = ballot_has<S>(v, pw) & mine;
         const unsigned long long cmask = __ballot(v.v[S - 1] != kEmpty) & mine & ~hm;
         hits += (uint32_t)__popcll(hm);
         if constexpr (PV) {
-            if ((hm >> lane) & 1ull) tally_hit<S, PV>(pr, b * S + bucket_pos<S>(v, pw), pbk & 0xFFFFu);
+            if ((hm >> lane) & 1ull) tally_hit<S, PV>(pr, b * S + bucket_pos<S>(v, pw), pk);
         }
-        const bool cont = (cmask >> lane) & 1ull;
-        pbk = cont ? ((((b + 1) & bmask) << 16) | (pbk & 0xFFFFu)) : pbk;
+        pb = ((cmask >> lane) & 1ull) ? b : pb;
         pm = cmask;
     };
 
-    // Resolve one bucket read; `act` limits it to lanes in range (ragged chunk).
     auto resolve = [&](const Bucket<S>& v, uint32_t w, uint32_t b, uint32_t kk, unsigned long long actm) {
         const unsigned long long hm = ballot_has<S>(v, w) & actm;
         const unsigned long long cm = __ballot(v.v[S - 1] != kEmpty) & actm & ~hm;
@@ -241,27 +268,21 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
             while (cm & pm) step_parked();
             const bool cont = !bucket_has<S>(v, w) & (v.v[S - 1] != kEmpty) & ((actm >> lane) & 1ull);
             pw = cont ? w : pw;
-            pbk = cont ? ((((b + 1) & bmask) << 16) | kk) : pbk;
+            pb = cont ? b : pb;
+            if constexpr (PV) pk = cont ? kk : pk;
             pm |= cm;
-            if ((uint32_t)__popcll(pm) >= 32u) step_parked();
+            if (__builtin_amdgcn_readfirstlane((uint32_t)__popcll(pm)) >= 32u) step_parked();
         }
     };
 
     // Full chunk: every lane active.
     auto fetch = [&](uint32_t& w, uint32_t& kk) {
-        if (ii >= end) {
-            do {
-                ++k;
-                const u32x2 rec = pr.P[k];
-                end = rec.x;
-                base = rec.y;
-            } while (ii >= end);
-        }
-        w = pr.col[(uint32_t)(base + ii)];
-        kk = k;
-        ii += 64u;
+        if (cur >= end) advance();
+        w = load();
+        if constexpr (PV) kk = k;
+        cur += step;
     };
-    auto probe_group = [&](const uint32_t (&w)[kUnroll], const uint32_t (&kk)[kUnroll], uint32_t n) {
+    auto probe_group = [&](const uint32_t (&w)[kUnroll], const uint32_t (&kk)[kUnroll]) {
         uint32_t b[kUnroll];
         Bucket<S> v[kUnroll];
 #pragma unroll
@@ -270,50 +291,43 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
             v[j] = read_bucket<S>(pr.slots, b[j]);
         }
 #pragma unroll
-        for (int j = 0; j < kUnroll; ++j)
-            if ((uint32_t)j < n) resolve(v[j], w[j], b[j], kk[j], ~0ull);
+        for (int j = 0; j < kUnroll; ++j) resolve(v[j], w[j], b[j], kk[j], ~0ull);
     };
 
     const uint32_t nfull = (hi - lo) >> 6;
-    if (nfull) {
+    uint32_t c = 0;
+    if (nfull >= 2u * kUnroll) {
         uint32_t wa[kUnroll], ka[kUnroll], wb[kUnroll], kb[kUnroll];
-        uint32_t c = 0;
-        uint32_t na = nfull < (uint32_t)kUnroll ? nfull : (uint32_t)kUnroll;
 #pragma unroll
-        for (int j = 0; j < kUnroll; ++j) {
-            wa[j] = 0; ka[j] = 0; wb[j] = 0; kb[j] = 0;
-            if ((uint32_t)j < na) fetch(wa[j], ka[j]);
+        for (int j = 0; j < kUnroll; ++j) { ka[j] = 0; kb[j] = 0; fetch(wa[j], ka[j]); }
+        c = kUnroll;
+        // invariant: group A (fetched) is pending; c chunks fetched
+        while (c + 2u * kUnroll <= nfull) {
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) fetch(wb[j], kb[j]);
+            probe_group(wa, ka);
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) fetch(wa[j], ka[j]);
+            probe_group(wb, kb);
+            c += 2u * kUnroll;
         }
-        c = na;
-        for (;;) {
-            const uint32_t nb = nfull - c < (uint32_t)kUnroll ? nfull - c : (uint32_t)kUnroll;
-#pragma unroll
-            for (int j = 0; j < kUnroll; ++j)
-                if ((uint32_t)j < nb) fetch(wb[j], kb[j]);
-            probe_group(wa, ka, na);
-            c += nb;
-            if (nb == 0) break;
-            na = nfull - c < (uint32_t)kUnroll ? nfull - c : (uint32_t)kUnroll;
-#pragma unroll
-            for (int j = 0; j < kUnroll; ++j)
-                if ((uint32_t)j < na) fetch(wa[j], ka[j]);
-            probe_group(wb, kb, nb);
-            c += na;
-            if (na == 0) break;
-        }
+        probe_group(wa, ka);
+    }
+    // Leftover full chunks, one at a time.
+    for (; c < nfull; ++c) {
+        uint32_t w, kk = 0;
+        fetch(w, kk);
+        const uint32_t b = hash_of<HK>(w, pr.B);
+        const Bucket<S> v = read_bucket<S>(pr.slots, b);
+        resolve(v, w, b, kk, ~0ull);
     }
     // Ragged last chunk: lanes past hi sit out.
-    if (ii - (uint32_t)lane < hi) {
-        const bool act = ii < hi;
+    if (lo + (nfull << 6) < hi) {
+        const bool act = lo + (nfull << 6) + (uint32_t)lane < hi;
         uint32_t w = 0;
         if (act) {
-            while (ii >= end) {
-                ++k;
-                const u32x2 rec = pr.P[k];
-                end = rec.x;
-                base = rec.y;
-            }
-            w = pr.col[(uint32_t)(base + ii)];
+            if (cur >= end) advance();
+            w = load();
         }
         const uint32_t b = hash_of<HK>(w, pr.B);
         const Bucket<S> v = read_bucket<S>(pr.slots, b);
@@ -364,30 +378,37 @@ __device__ __forceinline__ unsigned long long probe_range_global(const Probe& pr
 
 template <int S, bool PV, int HK, bool DEFER>
 __device__ __forceinline__ unsigned long long probe_range(const Probe& pr, uint32_t d, uint32_t lo, uint32_t hi,
-                                                          int lane) {
-    if constexpr (DEFER) return probe_range_lds<S, PV, HK>(pr, d, lo, hi, lane);
-    else return probe_range_global<S, PV, HK>(pr, d, lo, hi, lane);
+                                                          int lane, bool wide) {
+    if constexpr (DEFER) {
+        if (wide) return probe_range_lds<S, PV, HK, true>(pr, d, lo, hi, lane);
+        return probe_range_lds<S, PV, HK, false>(pr, d, lo, hi, lane);
+    } else {
+        return probe_range_global<S, PV, HK>(pr, d, lo, hi, lane);
+    }
 }
 
 // Process vertex u with a group of `gsz` lanes (one wavefront, or the workgroup when WG).
 template <int S, bool PV, int HK, bool WG, bool DEFER>
-__device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t* tbl, int gl, int gsz,
-                                        int gwave, int gnw, int lane, uint32_t* s_wsum, unsigned long long& acc) {
+__device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t* tbl, uint64_t avail, int gl,
+                                        int gsz, int gwave, int gnw, int lane, uint32_t* s_wsum,
+                                        unsigned long long& acc) {
     u = __builtin_amdgcn_readfirstlane(u);
     gwave = __builtin_amdgcn_readfirstlane(gwave);
     const int64_t beg = a.off[u];
     const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(a.off[u + 1] - beg));
-    const Geometry g = geometry(d, S, a.load_pct, PV);
+    const Geometry g = geometry_fit(d, S, a.load_pct, PV, avail);
     uint32_t* slots = tbl;
     uint32_t* len = tbl + g.o_len;
     u32x2* P = reinterpret_cast<u32x2*>(tbl + g.o_P);
-    uint32_t* selem = tbl + g.o_selem;
+    uint32_t* tslot = tbl + g.o_tslot;
     uint32_t* tally = tbl + g.o_tally;
 
     for (uint32_t x = gl; x < g.B * S; x += gsz) slots[x] = kEmpty;
     for (uint32_t x = gl; x < g.B; x += gsz) len[x] = 0;
-    if constexpr (PV)
+    if constexpr (PV) {
+        for (uint32_t x = gl; x < g.B * S; x += gsz) tslot[x] = 0;
         for (uint32_t x = gl; x < d; x += gsz) tally[x] = 0;
+    }
     group_sync<WG>();
 
     // Build the table of N+(u); record each out-neighbour's 2-hop list (length, start).
@@ -400,7 +421,6 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
             b = (b + 1) & g.mask;
         }
         slots[b * S + pos] = w;
-        if constexpr (PV) selem[b * S + pos] = p;
         const int64_t o0 = a.off[w], o1 = a.off[w + 1];
         P[p] = u32x2{(uint32_t)(o1 - o0), (uint32_t)o0};
     }
@@ -440,8 +460,8 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
     const uint32_t W = __builtin_amdgcn_readfirstlane(carry);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * gwave) / gnw));
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * (gwave + 1)) / gnw));
-    const Probe pr{a.col, slots, P, selem, tally, g.B};
-    const unsigned long long hits = probe_range<S, PV, HK, DEFER>(pr, d, lo, hi, lane);
+    const Probe pr{a.col, slots, P, tslot, tally, g.B};
+    const unsigned long long hits = probe_range<S, PV, HK, DEFER>(pr, d, lo, hi, lane, a.wide);
     if (a.gid) {
         if (lane == 0 && hits) atomicAdd(&a.totals[a.gid[u]], hits);
     } else {
@@ -454,6 +474,10 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
         for (uint32_t p = gl; p < d; p += gsz) {
             const uint32_t t = tally[p];
             if (t) atomicAdd(&a.tv[a.col[beg + p]], (unsigned long long)t);
+        }
+        for (uint32_t x = gl; x < g.B * S; x += gsz) {
+            const uint32_t t = tslot[x];
+            if (t) atomicAdd(&a.tv[slots[x]], (unsigned long long)t);
         }
     }
     group_sync<WG>();  // the table memory is reused by the next vertex
@@ -478,7 +502,7 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_hub) break;
-            process<S, PV, HK, true, false>(a, a.items[j], gt, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
+            process<S, PV, HK, true, false>(a, a.items[j], gt, a.hub_words, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
         }
     }
     // Workgroup bin: the table fills the workgroup's LDS.
@@ -489,7 +513,7 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_wg) break;
-            process<S, PV, HK, true, true>(a, a.items[n_hub + j], lds, tid, blockDim.x, wave, nw, lane, s_wsum,
+            process<S, PV, HK, true, true>(a, a.items[n_hub + j], lds, a.table_words, tid, blockDim.x, wave, nw, lane, s_wsum,
                                            acc);
         }
     }
@@ -504,7 +528,7 @@ __global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
             if (j0 >= n_wave) break;
             const uint32_t j1 = (j0 + a.chunk < n_wave) ? j0 + a.chunk : n_wave;
             for (uint32_t j = j0; j < j1; ++j)
-                process<S, PV, HK, false, true>(a, a.items[base + j], slice, lane, 64, 0, 1, lane, nullptr, acc);
+                process<S, PV, HK, false, true>(a, a.items[base + j], slice, a.slice_words, lane, 64, 0, 1, lane, nullptr, acc);
         }
     }
 

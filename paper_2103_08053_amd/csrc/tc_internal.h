@@ -28,11 +28,11 @@ static_assert(sizeof(GraphMeta) == 256, "meta is one 256-byte block");
 // Hash-table geometry for a vertex with d out-neighbours, shared by the host
 // (capacity per bin) and the kernels (layout in LDS or in global memory).
 // Layout in 32-bit words:
-//   slots[B*S] | len[B] | pad to 4 | P[2d] | (per-vertex mode) selem[B*S] | tally[d]
+//   slots[B*S] | len[B] | pad to 4 | P[2d] | (per-vertex mode) tslot[B*S] | tally[d]
 // B is the smallest power of two with B*S > d and B*S*load >= d, so every
 // probe chain ends at a bucket with a free slot.
 struct Geometry {
-    uint32_t B, mask, o_len, o_P, o_selem, o_tally, words;
+    uint32_t B, mask, o_len, o_P, o_tslot, o_tally, words;
 };
 
 __host__ __device__ inline uint32_t next_pow2(uint32_t x) {
@@ -41,18 +41,40 @@ __host__ __device__ inline uint32_t next_pow2(uint32_t x) {
     return p;
 }
 
+// Layout for d elements in B buckets.
+__host__ __device__ inline Geometry geometry_b(uint32_t d, uint32_t S, uint32_t B, bool pv) {
+    Geometry g;
+    g.B = B;
+    g.mask = B - 1;
+    g.o_len = B * S;
+    g.o_P = (g.o_len + B + 3u) & ~3u;
+    g.o_tslot = g.o_P + 2 * d;
+    g.o_tally = g.o_tslot + (pv ? B * S : 0);
+    g.words = (g.o_tally + (pv ? d : 0) + 3u) & ~3u;
+    return g;
+}
+
+// The smallest table the load factor allows (used to decide which bin a vertex fits).
 __host__ __device__ inline Geometry geometry(uint32_t d, uint32_t S, uint32_t load_pct, bool pv) {
     uint32_t need = (d + S) / S;                                // B*S > d
     uint32_t c = (uint32_t)(((uint64_t)d * 100 + (uint64_t)S * load_pct - 1) / ((uint64_t)S * load_pct));
     if (c > need) need = c;
-    Geometry g;
-    g.B = next_pow2(need);
-    g.mask = g.B - 1;
-    g.o_len = g.B * S;
-    g.o_P = (g.o_len + g.B + 3u) & ~3u;
-    g.o_selem = g.o_P + 2 * d;
-    g.o_tally = g.o_selem + (pv ? g.B * S : 0);
-    g.words = (g.o_tally + (pv ? d : 0) + 3u) & ~3u;
+    return geometry_b(d, S, next_pow2(need), pv);
+}
+
+// The table actually used: the minimal one grown (doubling B) while it fits
+// `avail` words and holds at most max(64, 8 d) slots, so a vertex whose
+// region has room gets a lightly loaded table (fewer full buckets to walk).
+__host__ __device__ inline Geometry geometry_fit(uint32_t d, uint32_t S, uint32_t load_pct, bool pv,
+                                                 uint64_t avail) {
+    Geometry g = geometry(d, S, load_pct, pv);
+    const uint64_t cap = 8ull * d > 64ull ? 8ull * d : 64ull;
+    for (;;) {
+        if ((uint64_t)g.B * 2 * S > cap) break;
+        const Geometry h = geometry_b(d, S, g.B * 2, pv);
+        if (h.words > avail) break;
+        g = h;
+    }
     return g;
 }
 
@@ -127,8 +149,10 @@ struct CountArgs {
     unsigned long long hub_words;
     uint32_t hub_wgs;
     uint32_t slice_words;            // per-wavefront LDS slice
+    uint32_t table_words;            // LDS words of the workgroup table region
     uint32_t load_pct;
     uint32_t chunk;
+    uint32_t wide;                   // col spans 4 GiB or more: 64-bit addressing in the probe
 };
 
 // tc_prep.hip

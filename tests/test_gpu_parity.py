@@ -113,6 +113,7 @@ FORCED = [
     dict(hash_kind=1), dict(light_chunk=1), dict(light_chunk=7), dict(flags=1), dict(flags=8),
     dict(wg_waves=1), dict(wg_waves=4), dict(wg_waves=16, wg_lds_bytes=131072),
     dict(grid_wgs=3), dict(grid_wgs=1, flags=4), dict(wave_max_dplus=8),
+    dict(flags=16), dict(flags=16 | 2, slots_per_bucket=1, load_factor_pct=100),   # 64-bit list addressing
 ]
 
 

@@ -84,7 +84,7 @@ tc_status check_params(const tc_params* p) {
     if (p->load_factor_pct < 10 || p->load_factor_pct > 100) return TC_E_INVALID;
     if (p->hash_kind > 1) return TC_E_INVALID;
     if (p->light_chunk < 1 || p->light_chunk > 256) return TC_E_INVALID;
-    if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SORT_LISTS | TC_F_WIDE_ADDR))
+    if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SCATTER_CSR | TC_F_WIDE_ADDR))
         return TC_E_INVALID;
     return TC_OK;
 }
@@ -102,7 +102,7 @@ tc::BinCaps bin_caps(const tc_params& p) {
     c.force_wg = (p.flags & TC_F_FORCE_WG) != 0;
     c.force_hub = (p.flags & TC_F_FORCE_HUB) != 0;
     c.lpt = (p.flags & TC_F_NO_LPT) == 0;
-    c.sort_lists = (p.flags & TC_F_SORT_LISTS) != 0;
+    c.scatter_csr = (p.flags & TC_F_SCATTER_CSR) != 0;
     return c;
 }
 

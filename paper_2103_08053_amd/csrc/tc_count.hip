@@ -116,6 +116,15 @@ __device__ __forceinline__ unsigned long long ballot_has(const Bucket<S>& v, uin
     return m;
 }
 
+// Byte offset of w within a bucket that contains it (j * 4).
+template <int S>
+__device__ __forceinline__ uint32_t bucket_pos4(const Bucket<S>& v, uint32_t w) {
+    uint32_t j4 = 4u * (S - 1);
+#pragma unroll
+    for (int j = S - 2; j >= 0; --j) j4 = (v.v[j] == w) ? 4u * j : j4;
+    return j4;
+}
+
 // Index of w within a bucket that contains it.
 template <int S>
 __device__ __forceinline__ uint32_t bucket_pos(const Bucket<S>& v, uint32_t w) {
@@ -171,6 +180,15 @@ template <int S, bool PV>
 __device__ __forceinline__ void tally_hit(const Probe& pr, uint32_t s, uint32_t k) {
     if constexpr (PV) {
         atomicAdd(&pr.tslot[s], 1u);
+        atomicAdd(&pr.tally[k], 1u);
+    }
+}
+
+// Per-vertex tallies of a hit in bucket b at byte offset j4 of the bucket.
+template <int S, bool PV>
+__device__ __forceinline__ void tally_hit4(const Probe& pr, uint32_t b, uint32_t j4, uint32_t k) {
+    if constexpr (PV) {
+        atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(pr.tslot) + b * (4u * S) + j4), 1u);
         atomicAdd(&pr.tally[k], 1u);
     }
 }
@@ -250,7 +268,7 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         const unsigned long long cmask = __ballot(v.v[S - 1] != kEmpty) & mine & ~hm;
         hits += (uint32_t)__popcll(hm);
         if constexpr (PV) {
-            if ((hm >> lane) & 1ull) tally_hit<S, PV>(pr, b * S + bucket_pos<S>(v, pw), pk);
+            if ((hm >> lane) & 1ull) tally_hit4<S, PV>(pr, b, bucket_pos4<S>(v, pw), pk);
         }
         pb = ((cmask >> lane) & 1ull) ? b : pb;
         pm = cmask;
@@ -261,8 +279,7 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         const unsigned long long cm = __ballot(v.v[S - 1] != kEmpty) & actm & ~hm;
         hits += (uint32_t)__popcll(hm);
         if constexpr (PV) {
-            if (bucket_has<S>(v, w) & ((actm >> lane) & 1ull))
-                tally_hit<S, PV>(pr, b * S + bucket_pos<S>(v, w), kk);
+            if (bucket_has<S>(v, w) & ((actm >> lane) & 1ull)) tally_hit4<S, PV>(pr, b, bucket_pos4<S>(v, w), kk);
         }
         if (cm) {
             while (cm & pm) step_parked();

@@ -119,7 +119,7 @@ struct BuildTemp {
 
 struct BinCaps {
     uint32_t wave_cap, wg_cap;
-    bool force_wg, force_hub, lpt, sort_lists;
+    bool force_wg, force_hub, lpt, scatter_csr;
 };
 
 struct Layout {

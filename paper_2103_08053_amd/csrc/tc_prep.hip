@@ -11,7 +11,8 @@
 //     its rank, so out-neighbour lists hold ranks and hashing the low bits of
 //     a rank spreads neighbours of similar degree over consecutive buckets
 //     (the reordering idea of Section 4.1);
-//  5. CSR by counting sort (int64 offsets);
+//  5. CSR: radix sort of the oriented keys, row lengths from key runs, scan
+//     (int64 offsets); lists come out sorted by rank;
 //  6. scheduling (Section 4.3): out-degree d+ and collective work
 //     W(u) = sum of d+(v) over out-neighbours v (the collective degree of
 //     Equation 2); vertices with d+ < 2 or W = 0 are skipped, the rest go to
@@ -165,6 +166,39 @@ __global__ void k_orient_fill(const unsigned long long* __restrict__ keys, uint3
     }
 }
 
+// Oriented keys (rank_lo << nb | rank_hi) for a sort-based CSR build; the
+// entries past m get the sentinel so they sort last.
+__global__ void k_orient_keys(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
+                              const GraphMeta* meta, const uint32_t* __restrict__ rank, unsigned long long sentinel,
+                              unsigned long long* __restrict__ okeys) {
+    const uint64_t m = meta->m;
+    const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i < m) {
+            const unsigned long long k = keys[i];
+            const uint32_t ra = rank[(uint32_t)(k >> nb)], rb = rank[(uint32_t)(k & mask)];
+            okeys[i] = ((unsigned long long)(ra < rb ? ra : rb) << nb) | (ra < rb ? rb : ra);
+        } else {
+            okeys[i] = sentinel;
+        }
+    }
+}
+
+// From sorted oriented keys: col[i] = head, and d+ of each row as its run
+// length (the run's first key subtracts its index, its last adds index + 1).
+__global__ void k_csr_runs(const unsigned long long* __restrict__ okeys, uint32_t nb, uint64_t cap,
+                           const GraphMeta* meta, uint32_t* __restrict__ dplus, uint32_t* __restrict__ col) {
+    const uint64_t m = meta->m;
+    const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap && i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = okeys[i];
+        const uint32_t s = (uint32_t)(k >> nb);
+        col[i] = (uint32_t)(k & mask);
+        if (i == 0 || (uint32_t)(okeys[i - 1] >> nb) != s) atomicSub(&dplus[s], (uint32_t)i);
+        if (i + 1 == m || (uint32_t)(okeys[i + 1] >> nb) != s) atomicAdd(&dplus[s], (uint32_t)(i + 1));
+    }
+}
+
 // One thread per vertex: d+, W(u), bin, and the sort key (bin << 40 | reversed work).
 __global__ void k_schedule(const int64_t* __restrict__ off, const uint32_t* __restrict__ col, uint32_t n,
                            BinCaps caps, GraphMeta* meta, unsigned long long* __restrict__ skey) {
@@ -245,10 +279,6 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
     sz = 0;
     if (rocprim::radix_sort_pairs(nullptr, sz, k64, k64, rocprim::counting_iterator<uint32_t>(0), u32p,
                                   (size_t)n, 0, 42) == hipSuccess && sz > best) best = sz;
-    sz = 0;
-    if (m_in > 0 && n > 0 &&
-        rocprim::segmented_radix_sort_keys(nullptr, sz, u32p, u32p, (unsigned int)m_in, n, i64p, i64p + 1, 0, 32) ==
-            hipSuccess && sz > best) best = sz;
     return best;
 }
 
@@ -299,22 +329,31 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     }
 
     // 4-5: orientation and CSR in rank space.
-    hipLaunchKernelGGL(k_orient_count, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta,
-                       g.rank, t.dplus);
-    TC_TRY(hipGetLastError());
-    tmp = t.sort_tmp_bytes;
-    TC_TRY(rocprim::exclusive_scan(t.sort_tmp, tmp, t.dplus, g.off, (unsigned long long)0, (size_t)n + 1,
-                                   rocprim::plus<unsigned long long>(), stream));
-    TC_TRY(fill_u32(t.deg, 0, (size_t)n + 1, stream));
-    hipLaunchKernelGGL(k_orient_fill, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta,
-                       g.rank, g.off, t.deg, g.col);
-    TC_TRY(hipGetLastError());
-    if (caps.sort_lists) {
-        uint32_t* col_tmp = reinterpret_cast<uint32_t*>(t.keys_b);
+    if (!caps.scatter_csr) {
+        // Sort the oriented keys: rows come out contiguous and each list sorted by rank.
+        hipLaunchKernelGGL(k_orient_keys, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta,
+                           g.rank, sentinel, t.keys_b);
+        TC_TRY(hipGetLastError());
         tmp = t.sort_tmp_bytes;
-        TC_TRY(rocprim::segmented_radix_sort_keys(t.sort_tmp, tmp, g.col, col_tmp, (unsigned int)m_in, n, g.off,
-                                                  g.off + 1, 0, 32, stream));
-        TC_TRY(hipMemcpyAsync(g.col, col_tmp, sizeof(uint32_t) * m_in, hipMemcpyDeviceToDevice, stream));
+        TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, t.keys_b, t.keys_a, (size_t)m_in, 0, 2 * nb, stream));
+        hipLaunchKernelGGL(k_csr_runs, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta,
+                           t.dplus, g.col);
+        TC_TRY(hipGetLastError());
+        tmp = t.sort_tmp_bytes;
+        TC_TRY(rocprim::exclusive_scan(t.sort_tmp, tmp, t.dplus, g.off, (unsigned long long)0, (size_t)n + 1,
+                                       rocprim::plus<unsigned long long>(), stream));
+    } else {
+        // Counting sort: out-degrees, offsets, then an atomic scatter (list order unspecified).
+        hipLaunchKernelGGL(k_orient_count, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in,
+                           g.meta, g.rank, t.dplus);
+        TC_TRY(hipGetLastError());
+        tmp = t.sort_tmp_bytes;
+        TC_TRY(rocprim::exclusive_scan(t.sort_tmp, tmp, t.dplus, g.off, (unsigned long long)0, (size_t)n + 1,
+                                       rocprim::plus<unsigned long long>(), stream));
+        TC_TRY(fill_u32(t.deg, 0, (size_t)n + 1, stream));
+        hipLaunchKernelGGL(k_orient_fill, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in,
+                           g.meta, g.rank, g.off, t.deg, g.col);
+        TC_TRY(hipGetLastError());
     }
 
     // 6: bins and largest-work-first order.

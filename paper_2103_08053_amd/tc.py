@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtrust_tc.so")
 
 TC_OK, TC_E_INVALID, TC_E_RANGE, TC_E_NOMEM, TC_E_DEVICE, TC_E_UNSUPPORTED, TC_E_BUSY = range(7)
-TC_F_NO_LPT, TC_F_FORCE_WG, TC_F_FORCE_HUB, TC_F_SORT_LISTS, TC_F_WIDE_ADDR = 0x1, 0x2, 0x4, 0x8, 0x10
+TC_F_NO_LPT, TC_F_FORCE_WG, TC_F_FORCE_HUB, TC_F_SCATTER_CSR, TC_F_WIDE_ADDR = 0x1, 0x2, 0x4, 0x8, 0x10
 
 EXPORTS = [
     "tc_default_params", "tc_create", "tc_destroy", "tc_set_params", "tc_get_params", "tc_status_str",

@@ -210,9 +210,9 @@ def run_serve(args):
     ctx0 = Context(0)
     alone = [ctx0.count(g.src, g.dst, g.n)[0] for g in pool]  # each graph counted on its own
     res = {}
+    pinned = [(g.n, serve._pinned(g.src), serve._pinned(g.dst)) for g in pool]  # one pinned copy per graph
     for mode in ("batched", "plain"):
-        reqs = [serve.make_request(i, pool[i % len(pool)].n, pool[i % len(pool)].src, pool[i % len(pool)].dst)
-                for i in range(len(arrivals))]
+        reqs = [serve.Request(i, *pinned[i % len(pool)]) for i in range(len(arrivals))]
         torch.cuda.synchronize()
         if mode == "batched":
             srv = serve.Server(0, hbm_budget=args.hbm_budget_gb << 30, max_batch=args.max_batch)

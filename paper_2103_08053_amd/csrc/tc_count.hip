@@ -72,6 +72,13 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
     return v;
 }
 
+// Sum of a per-lane value over the wavefront (butterfly of lane swaps).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -184,13 +191,10 @@ __device__ __forceinline__ void tally_hit(const Probe& pr, uint32_t s, uint32_t 
     }
 }
 
-// Per-vertex tallies of a hit in bucket b at byte offset j4 of the bucket.
-template <int S, bool PV>
-__device__ __forceinline__ void tally_hit4(const Probe& pr, uint32_t b, uint32_t j4, uint32_t k) {
-    if constexpr (PV) {
-        atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(pr.tslot) + b * (4u * S) + j4), 1u);
-        atomicAdd(&pr.tally[k], 1u);
-    }
+// Slot tally of a hit in bucket b at byte offset j4 of the bucket.
+template <int S>
+__device__ __forceinline__ void tally_slot4(const Probe& pr, uint32_t b, uint32_t j4) {
+    atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(pr.tslot) + b * (4u * S) + j4), 1u);
 }
 
 // Probe the flattened 2-hop range [lo, hi) of the current vertex with one
@@ -218,7 +222,7 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
                                                               int lane) {
     if (lo >= hi) return 0;
     const uint32_t bmask = pr.B - 1;
-    uint32_t hits = 0;  // wave-uniform; W < 2^32
+    uint32_t hits = 0;  // per lane; summed across the wavefront at the end (W < 2^32)
     // Cursor: record k holds the lane's next flattened index ii; pos = base_k + ii.
     uint32_t k, pos, lim, base;
     {
@@ -259,6 +263,9 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
     // Parked lookups: word, bucket (and k in per-vertex mode), mask of lanes holding one.
     uint32_t pw = 0, pb = 0, pk = 0;
     unsigned long long pm = 0;
+    // Per-vertex mode: hits of the lane's current out-neighbour k, added to tally[k] when k changes
+    // (hits of one chunk mostly share k; per-hit atomics on one address would serialise).
+    uint32_t acck = k, accn = 0;
 
     auto step_parked = [&]() {
         const unsigned long long mine = pm;
@@ -266,9 +273,12 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         const Bucket<S> v = read_bucket<S>(pr.slots, b);
         const unsigned long long hm = ballot_has<S>(v, pw) & mine;
         const unsigned long long cmask = __ballot(v.v[S - 1] != kEmpty) & mine & ~hm;
-        hits += (uint32_t)__popcll(hm);
+        hits += (uint32_t)((hm >> lane) & 1ull);
         if constexpr (PV) {
-            if ((hm >> lane) & 1ull) tally_hit4<S, PV>(pr, b, bucket_pos4<S>(v, pw), pk);
+            if ((hm >> lane) & 1ull) {
+                tally_slot4<S>(pr, b, bucket_pos4<S>(v, pw));
+                atomicAdd(&pr.tally[pk], 1u);
+            }
         }
         pb = ((cmask >> lane) & 1ull) ? b : pb;
         pm = cmask;
@@ -277,9 +287,16 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
     auto resolve = [&](const Bucket<S>& v, uint32_t w, uint32_t b, uint32_t kk, unsigned long long actm) {
         const unsigned long long hm = ballot_has<S>(v, w) & actm;
         const unsigned long long cm = __ballot(v.v[S - 1] != kEmpty) & actm & ~hm;
-        hits += (uint32_t)__popcll(hm);
+        hits += (uint32_t)(bucket_has<S>(v, w) & ((actm >> lane) & 1ull));
         if constexpr (PV) {
-            if (bucket_has<S>(v, w) & ((actm >> lane) & 1ull)) tally_hit4<S, PV>(pr, b, bucket_pos4<S>(v, w), kk);
+            const bool hit = bucket_has<S>(v, w) & ((actm >> lane) & 1ull);
+            if (kk != acck) {
+                if (accn) atomicAdd(&pr.tally[acck], accn);
+                acck = kk;
+                accn = 0;
+            }
+            accn += hit ? 1u : 0u;
+            if (hit) tally_slot4<S>(pr, b, bucket_pos4<S>(v, w));
         }
         if (cm) {
             while (cm & pm) step_parked();
@@ -294,7 +311,9 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
 
     // Full chunk: every lane active.
     auto fetch = [&](uint32_t& w, uint32_t& kk) {
-        if (cur >= end) advance();
+        if (__ballot(cur >= end)) {  // uniform test first: most chunks need no lane to advance
+            if (cur >= end) advance();
+        }
         w = load();
         if constexpr (PV) kk = k;
         cur += step;
@@ -351,7 +370,10 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         resolve(v, w, b, k, __ballot(act));
     }
     while (pm) step_parked();
-    return hits;
+    if constexpr (PV) {
+        if (accn) atomicAdd(&pr.tally[acck], accn);
+    }
+    return wave_sum(hits);
 }
 
 // The same walk with a per-lane cursor and lane-by-lane chain lookups, for

@@ -24,7 +24,8 @@ def test_served_results_equal_alone():
     alone = [ctx.count(g.src, g.dst, g.n)[0] for g in pool]
     arrivals = W.poisson_arrivals(400.0, 0.5, seed=3)
     say(f"[gpu] serving {len(arrivals)} requests")
-    reqs = [serve.make_request(i, pool[i % len(pool)].n, pool[i % len(pool)].src, pool[i % len(pool)].dst)
+    pinned = [serve.make_request(i, g.n, g.src, g.dst) for i, g in enumerate(pool)]
+    reqs = [serve.Request(i, pinned[i % len(pool)].n, pinned[i % len(pool)].src, pinned[i % len(pool)].dst)
             for i in range(len(arrivals))]
     srv = serve.Server(0, hbm_budget=2 << 30, max_batch=32)
     stats = srv.run(reqs, arrivals)

@@ -116,21 +116,31 @@ __global__ void k_fix_m(const unsigned long long* keys, unsigned long long senti
     meta->m = u;
 }
 
-// Degrees from the sorted, unique keys.  The lower endpoint of a key is
-// constant over a run of consecutive keys, so its degree is the run length:
-// the run's first key subtracts its index and the run's last key adds its
-// index + 1 (one atomic each, mod 2^32), which avoids hammering one counter
-// per hub vertex.  The upper endpoint counts with one atomic per key.
-__global__ void k_degree(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
-                         const GraphMeta* meta, uint32_t* __restrict__ deg) {
+// Upper endpoints of the unique keys; entries past m get a value above every id
+// (bit nb set, or all ones when ids take 32 bits) so they sort last.
+__global__ void k_upper(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap, const GraphMeta* meta,
+                        uint32_t* __restrict__ upper) {
     const uint64_t m = meta->m;
     const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x)
+        upper[i] = i < m ? (uint32_t)(keys[i] & mask) : (nb >= 32 ? 0xFFFFFFFFu : (1u << nb));
+}
+
+// Degrees from runs: the lower endpoints of the sorted unique keys and the
+// sorted upper endpoints both come in runs of equal ids, so each id's count
+// is a run length: the run's first element subtracts its index and its last
+// adds index + 1 (two atomics per run, mod 2^32), with no counter hammered
+// by a hub vertex.
+__global__ void k_degree(const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ upper, uint32_t nb,
+                         uint64_t cap, const GraphMeta* meta, uint32_t* __restrict__ deg) {
+    const uint64_t m = meta->m;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap && i < m; i += (uint64_t)gridDim.x * blockDim.x) {
-        const unsigned long long k = keys[i];
-        const uint32_t lo = (uint32_t)(k >> nb);
+        const uint32_t lo = (uint32_t)(keys[i] >> nb);
         if (i == 0 || (uint32_t)(keys[i - 1] >> nb) != lo) atomicSub(&deg[lo], (uint32_t)i);
         if (i + 1 == m || (uint32_t)(keys[i + 1] >> nb) != lo) atomicAdd(&deg[lo], (uint32_t)(i + 1));
-        atomicAdd(&deg[(uint32_t)(k & mask)], 1u);
+        const uint32_t hi = upper[i];
+        if (i == 0 || upper[i - 1] != hi) atomicSub(&deg[hi], (uint32_t)i);
+        if (i + 1 == m || upper[i + 1] != hi) atomicAdd(&deg[hi], (uint32_t)(i + 1));
     }
 }
 
@@ -268,6 +278,9 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
     uint32_t* u32p = nullptr;
     if (rocprim::radix_sort_keys(nullptr, sz, k64, k64, (size_t)m_in, 0, 2 * nb) == hipSuccess && sz > best) best = sz;
     sz = 0;
+    if (rocprim::radix_sort_keys(nullptr, sz, u32p, u32p, (size_t)m_in, 0, nb < 32 ? nb + 1 : 32) == hipSuccess &&
+        sz > best) best = sz;
+    sz = 0;
     if (rocprim::unique(nullptr, sz, k64, k64, u32p, (size_t)m_in) == hipSuccess && sz > best) best = sz;
     sz = 0;
     if (rocprim::radix_sort_pairs(nullptr, sz, u32p, u32p, rocprim::counting_iterator<uint32_t>(0), u32p,
@@ -308,9 +321,19 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     hipLaunchKernelGGL(k_fix_m, dim3(1), dim3(1), 0, stream, t.keys_a, sentinel, g.meta);
     TC_TRY(hipGetLastError());
 
-    // 3: degree, rank in (degree, id) order (stable sort keeps ids ascending among equal degrees).
-    hipLaunchKernelGGL(k_degree, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta, t.deg);
-    TC_TRY(hipGetLastError());
+    // 3: degree (from runs of the lower and of the sorted upper endpoints), rank in (degree, id)
+    // order (stable sort keeps ids ascending among equal degrees).
+    {
+        uint32_t* up_a = reinterpret_cast<uint32_t*>(t.keys_b);
+        uint32_t* up_b = up_a + m_in;
+        hipLaunchKernelGGL(k_upper, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta, up_a);
+        TC_TRY(hipGetLastError());
+        tmp = t.sort_tmp_bytes;
+        TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, up_a, up_b, (size_t)m_in, 0, nb < 32 ? nb + 1 : 32, stream));
+        hipLaunchKernelGGL(k_degree, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, up_b, nb, m_in,
+                           g.meta, t.deg);
+        TC_TRY(hipGetLastError());
+    }
     uint32_t deg_bits = 1;
     {
         const uint64_t dmax = (uint64_t)n - 1 < 2 * m_in ? (uint64_t)n - 1 : 2 * m_in;

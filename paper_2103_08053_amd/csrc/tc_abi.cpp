@@ -129,6 +129,7 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     o = 0;
     L.t_keys_a = o; o = align_up(o + 8 * (size_t)m_in);
     L.t_keys_b = o; o = align_up(o + 8 * (size_t)m_in);
+    L.t_aux = o;    o = align_up(o + 8 * (size_t)m_in);
     L.t_deg = o;    o = align_up(o + 4 * ((size_t)n + 1));
     L.t_dplus = o;  o = align_up(o + 4 * ((size_t)n + 1));
     L.t_order = o;  o = align_up(o + 4 * (size_t)n);
@@ -168,6 +169,7 @@ tc::BuildTemp temp_ptrs(void* temp, const Layout& L) {
     tc::BuildTemp t;
     t.keys_a = reinterpret_cast<unsigned long long*>(b + L.t_keys_a);
     t.keys_b = reinterpret_cast<unsigned long long*>(b + L.t_keys_b);
+    t.aux = reinterpret_cast<uint32_t*>(b + L.t_aux);
     t.deg = reinterpret_cast<uint32_t*>(b + L.t_deg);
     t.dplus = reinterpret_cast<uint32_t*>(b + L.t_dplus);
     t.order = reinterpret_cast<uint32_t*>(b + L.t_order);

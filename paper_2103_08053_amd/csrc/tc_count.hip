@@ -273,11 +273,12 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         const Bucket<S> v = read_bucket<S>(pr.slots, b);
         const unsigned long long hm = ballot_has<S>(v, pw) & mine;
         const unsigned long long cmask = __ballot(v.v[S - 1] != kEmpty) & mine & ~hm;
-        hits += (uint32_t)((hm >> lane) & 1ull);
+        if constexpr (!PV) hits += (uint32_t)((hm >> lane) & 1ull);
         if constexpr (PV) {
             if ((hm >> lane) & 1ull) {
                 tally_slot4<S>(pr, b, bucket_pos4<S>(v, pw));
                 atomicAdd(&pr.tally[pk], 1u);
+                ++hits;
             }
         }
         pb = ((cmask >> lane) & 1ull) ? b : pb;
@@ -287,15 +288,16 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
     auto resolve = [&](const Bucket<S>& v, uint32_t w, uint32_t b, uint32_t kk, unsigned long long actm) {
         const unsigned long long hm = ballot_has<S>(v, w) & actm;
         const unsigned long long cm = __ballot(v.v[S - 1] != kEmpty) & actm & ~hm;
-        hits += (uint32_t)(bucket_has<S>(v, w) & ((actm >> lane) & 1ull));
+        if constexpr (!PV) hits += (uint32_t)(bucket_has<S>(v, w) & ((actm >> lane) & 1ull));
         if constexpr (PV) {
             const bool hit = bucket_has<S>(v, w) & ((actm >> lane) & 1ull);
             if (kk != acck) {
                 if (accn) atomicAdd(&pr.tally[acck], accn);
+                hits += accn;
                 acck = kk;
                 accn = 0;
             }
-            accn += hit ? 1u : 0u;
+            accn += (uint32_t)hit;
             if (hit) tally_slot4<S>(pr, b, bucket_pos4<S>(v, w));
         }
         if (cm) {
@@ -372,6 +374,7 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
     while (pm) step_parked();
     if constexpr (PV) {
         if (accn) atomicAdd(&pr.tally[acck], accn);
+        hits += accn;  // hits of u = all v_k tallies: accumulated runs plus parked hits
     }
     return wave_sum(hits);
 }

@@ -17,7 +17,7 @@ constexpr uint32_t kHubWgs = 128;        // workgroups that take global-memory-t
 struct GraphMeta {
     unsigned long long m;           // oriented edges
     unsigned long long wplus;       // W+ = sum over oriented (u, v) of d+(v)
-    unsigned int m_unique;          // distinct keys after dedup (may include the removed-edge sentinel)
+    unsigned int reserved0;
     unsigned int max_dplus;
     unsigned int err;               // bit 0: some input id >= n
     unsigned int bins[4];           // vertex counts: hub, workgroup, wavefront, skipped (d+ < 2 or no 2-hop work)
@@ -108,6 +108,7 @@ struct BatchIn {
 struct BuildTemp {
     unsigned long long* keys_a;
     unsigned long long* keys_b;
+    uint32_t* aux;       // [2 m_in]: sorted upper endpoints, then the sorted oriented keys
     uint32_t* deg;       // [n + 1]; reused as the fill cursor
     uint32_t* dplus;     // [n + 1]
     uint32_t* order;     // [n]
@@ -127,7 +128,7 @@ struct Layout {
     // storage offsets
     size_t s_meta, s_off, s_col, s_rank, s_items, s_gid;
     // temp offsets
-    size_t t_keys_a, t_keys_b, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_sort;
+    size_t t_keys_a, t_keys_b, t_aux, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_sort;
     size_t sort_tmp_bytes;
     // scratch offsets
     size_t c_tv, c_heads, c_total, c_hub;

@@ -42,6 +42,32 @@ inline uint32_t id_bits(uint32_t n) {  // bits to hold any id < n (at least 1)
     return b;
 }
 
+// 1 for the first key of each run of equal keys (and not the sentinel): the
+// inclusive scan of these flags numbers the distinct edges.
+struct FirstOfRun {
+    const unsigned long long* keys;
+    unsigned long long sentinel;
+    __device__ uint32_t operator()(uint64_t i) const {
+        const unsigned long long k = keys[i];
+        return (k != sentinel && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+    }
+};
+
+// d+(col[e]) for edge e (0 past the last edge), for the collective-degree scan.
+struct HeadOutDegree {
+    const uint32_t* col;
+    const uint32_t* dplus;
+    const GraphMeta* meta;
+    __device__ unsigned long long operator()(uint64_t e) const {
+        return e < meta->m ? (unsigned long long)dplus[col[e]] : 0ull;
+    }
+};
+
+__device__ __forceinline__ bool first_of_run(const unsigned long long* keys, uint64_t i, unsigned long long sentinel) {
+    const unsigned long long k = keys[i];
+    return k != sentinel && (i == 0 || keys[i - 1] != k);
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t words) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -109,38 +135,45 @@ __global__ void k_gid(const uint32_t* __restrict__ order, uint32_t n, const unsi
         gid[r] = owner(voff, k, order[r]);
 }
 
-// m = number of distinct keys minus the sentinel (present at most once, last).
-__global__ void k_fix_m(const unsigned long long* keys, unsigned long long sentinel, GraphMeta* meta) {
-    uint32_t u = meta->m_unique;
-    if (u > 0 && keys[u - 1] == sentinel) --u;
-    meta->m = u;
+// m = number of distinct edges (last value of the first-of-run scan).
+__global__ void k_set_m(const uint32_t* first_scan, uint64_t m_in, GraphMeta* meta) {
+    meta->m = m_in ? first_scan[m_in - 1] : 0;
 }
 
-// Upper endpoints of the unique keys; entries past m get a value above every id
-// (bit nb set, or all ones when ids take 32 bits) so they sort last.
-__global__ void k_upper(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap, const GraphMeta* meta,
-                        uint32_t* __restrict__ upper) {
-    const uint64_t m = meta->m;
+// Upper endpoints of the distinct edges (sorted keys, duplicates in place);
+// duplicates and sentinels get a value above every id (bit nb set, or all
+// ones when ids take 32 bits) so they sort last.
+__global__ void k_upper(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
+                        unsigned long long sentinel, uint32_t* __restrict__ upper) {
     const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
+    const uint32_t above = nb >= 32 ? 0xFFFFFFFFu : (1u << nb);
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x)
-        upper[i] = i < m ? (uint32_t)(keys[i] & mask) : (nb >= 32 ? 0xFFFFFFFFu : (1u << nb));
+        upper[i] = first_of_run(keys, i, sentinel) ? (uint32_t)(keys[i] & mask) : above;
 }
 
-// Degrees from runs: the lower endpoints of the sorted unique keys and the
-// sorted upper endpoints both come in runs of equal ids, so each id's count
-// is a run length: the run's first element subtracts its index and its last
-// adds index + 1 (two atomics per run, mod 2^32), with no counter hammered
-// by a hub vertex.
-__global__ void k_degree(const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ upper, uint32_t nb,
-                         uint64_t cap, const GraphMeta* meta, uint32_t* __restrict__ deg) {
+// Degrees from runs.  Lower endpoints: the sorted keys come in runs of equal
+// lower id; the run's distinct edges are counted with the first-of-run scan
+// (its first element subtracts the scan before it, its last adds the scan at
+// it).  Upper endpoints: the sorted upper ids of the distinct edges, counted
+// by run length (first subtracts its index, last adds index + 1).  Two
+// atomics per run (mod 2^32): no counter is hammered by a hub vertex.
+__global__ void k_degree(const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ first_scan,
+                         const uint32_t* __restrict__ upper, uint32_t nb, uint64_t cap, unsigned long long sentinel,
+                         const GraphMeta* meta, uint32_t* __restrict__ deg) {
     const uint64_t m = meta->m;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap && i < m; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t lo = (uint32_t)(keys[i] >> nb);
-        if (i == 0 || (uint32_t)(keys[i - 1] >> nb) != lo) atomicSub(&deg[lo], (uint32_t)i);
-        if (i + 1 == m || (uint32_t)(keys[i + 1] >> nb) != lo) atomicAdd(&deg[lo], (uint32_t)(i + 1));
-        const uint32_t hi = upper[i];
-        if (i == 0 || upper[i - 1] != hi) atomicSub(&deg[hi], (uint32_t)i);
-        if (i + 1 == m || upper[i + 1] != hi) atomicAdd(&deg[hi], (uint32_t)(i + 1));
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = keys[i];
+        if (k != sentinel) {
+            // the sentinel's lower bits exceed every valid lower id, so runs end at it
+            const uint32_t lo = (uint32_t)(k >> nb);
+            if (i == 0 || (uint32_t)(keys[i - 1] >> nb) != lo) atomicSub(&deg[lo], i ? first_scan[i - 1] : 0u);
+            if (i + 1 == cap || (uint32_t)(keys[i + 1] >> nb) != lo) atomicAdd(&deg[lo], first_scan[i]);
+        }
+        if (i < m) {
+            const uint32_t hi = upper[i];
+            if (i == 0 || upper[i - 1] != hi) atomicSub(&deg[hi], (uint32_t)i);
+            if (i + 1 == m || upper[i + 1] != hi) atomicAdd(&deg[hi], (uint32_t)(i + 1));
+        }
     }
 }
 
@@ -150,11 +183,11 @@ __global__ void k_rank(const uint32_t* __restrict__ order, uint32_t n, uint32_t*
 }
 
 __global__ void k_orient_count(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
-                               const GraphMeta* meta, const uint32_t* __restrict__ rank,
+                               unsigned long long sentinel, const uint32_t* __restrict__ rank,
                                uint32_t* __restrict__ dplus) {
-    const uint64_t m = meta->m;
     const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap && i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (!first_of_run(keys, i, sentinel)) continue;
         const unsigned long long k = keys[i];
         const uint32_t ra = rank[(uint32_t)(k >> nb)], rb = rank[(uint32_t)(k & mask)];
         atomicAdd(&dplus[ra < rb ? ra : rb], 1u);
@@ -162,12 +195,12 @@ __global__ void k_orient_count(const unsigned long long* __restrict__ keys, uint
 }
 
 __global__ void k_orient_fill(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
-                              const GraphMeta* meta, const uint32_t* __restrict__ rank,
+                              unsigned long long sentinel, const uint32_t* __restrict__ rank,
                               const int64_t* __restrict__ off, uint32_t* __restrict__ cursor,
                               uint32_t* __restrict__ col) {
-    const uint64_t m = meta->m;
     const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap && i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
+        if (!first_of_run(keys, i, sentinel)) continue;
         const unsigned long long k = keys[i];
         const uint32_t ra = rank[(uint32_t)(k >> nb)], rb = rank[(uint32_t)(k & mask)];
         const uint32_t s = ra < rb ? ra : rb, d = ra < rb ? rb : ra;
@@ -176,15 +209,14 @@ __global__ void k_orient_fill(const unsigned long long* __restrict__ keys, uint3
     }
 }
 
-// Oriented keys (rank_lo << nb | rank_hi) for a sort-based CSR build; the
-// entries past m get the sentinel so they sort last.
+// Oriented keys (rank_lo << nb | rank_hi) of the distinct edges for a
+// sort-based CSR build; duplicates and sentinels stay the sentinel (sort last).
 __global__ void k_orient_keys(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
-                              const GraphMeta* meta, const uint32_t* __restrict__ rank, unsigned long long sentinel,
+                              const uint32_t* __restrict__ rank, unsigned long long sentinel,
                               unsigned long long* __restrict__ okeys) {
-    const uint64_t m = meta->m;
     const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
-        if (i < m) {
+        if (first_of_run(keys, i, sentinel)) {
             const unsigned long long k = keys[i];
             const uint32_t ra = rank[(uint32_t)(k >> nb)], rb = rank[(uint32_t)(k & mask)];
             okeys[i] = ((unsigned long long)(ra < rb ? ra : rb) << nb) | (ra < rb ? rb : ra);
@@ -209,8 +241,10 @@ __global__ void k_csr_runs(const unsigned long long* __restrict__ okeys, uint32_
     }
 }
 
-// One thread per vertex: d+, W(u), bin, and the sort key (bin << 40 | reversed work).
-__global__ void k_schedule(const int64_t* __restrict__ off, const uint32_t* __restrict__ col, uint32_t n,
+// One thread per vertex: d+, W(u) = sum of d+(v) over v in N+(u) (from the
+// inclusive scan of d+(col[e]) over the edges), bin, and the sort key
+// (bin << 40 | reversed work).
+__global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long long* __restrict__ wscan, uint32_t n,
                            BinCaps caps, GraphMeta* meta, unsigned long long* __restrict__ skey) {
     __shared__ unsigned long long s_w;
     __shared__ unsigned int s_max, s_bins[4];
@@ -220,11 +254,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const uint32_t* __re
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         const int64_t b = off[r], e = off[r + 1];
         const uint32_t d = (uint32_t)(e - b);
-        unsigned long long w = 0;
-        for (int64_t p = b; p < e; ++p) {
-            const uint32_t v = col[p];
-            w += (unsigned long long)(off[v + 1] - off[v]);
-        }
+        const unsigned long long w = d ? wscan[e - 1] - (b ? wscan[b - 1] : 0ull) : 0ull;
         uint32_t bin;
         if (d < 2 || w == 0) bin = 3;
         else if (caps.force_hub || d > caps.wg_cap) bin = 0;
@@ -281,11 +311,21 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
     if (rocprim::radix_sort_keys(nullptr, sz, u32p, u32p, (size_t)m_in, 0, nb < 32 ? nb + 1 : 32) == hipSuccess &&
         sz > best) best = sz;
     sz = 0;
-    if (rocprim::unique(nullptr, sz, k64, k64, u32p, (size_t)m_in) == hipSuccess && sz > best) best = sz;
-    sz = 0;
     if (rocprim::radix_sort_pairs(nullptr, sz, u32p, u32p, rocprim::counting_iterator<uint32_t>(0), u32p,
                                   (size_t)n, 0, 32) == hipSuccess && sz > best) best = sz;
     sz = 0;
+    {
+        auto flags = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
+                                                      FirstOfRun{k64, 0ull});
+        if (rocprim::inclusive_scan(nullptr, sz, flags, u32p, (size_t)m_in, rocprim::plus<uint32_t>()) == hipSuccess &&
+            sz > best) best = sz;
+        sz = 0;
+        auto heads = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
+                                                      HeadOutDegree{u32p, u32p, nullptr});
+        if (rocprim::inclusive_scan(nullptr, sz, heads, k64, (size_t)m_in, rocprim::plus<unsigned long long>()) ==
+                hipSuccess && sz > best) best = sz;
+        sz = 0;
+    }
     int64_t* i64p = nullptr;
     if (rocprim::exclusive_scan(nullptr, sz, u32p, i64p, (unsigned long long)0, (size_t)n + 1,
                                 rocprim::plus<unsigned long long>()) == hipSuccess && sz > best) best = sz;
@@ -315,23 +355,30 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     TC_TRY(hipGetLastError());
     tmp = t.sort_tmp_bytes;
     TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, t.keys_a, t.keys_b, (size_t)m_in, 0, 2 * nb, stream));
-    tmp = t.sort_tmp_bytes;
-    TC_TRY(rocprim::unique(t.sort_tmp, tmp, t.keys_b, t.keys_a, &g.meta->m_unique, (size_t)m_in,
-                           rocprim::equal_to<unsigned long long>(), stream));
-    hipLaunchKernelGGL(k_fix_m, dim3(1), dim3(1), 0, stream, t.keys_a, sentinel, g.meta);
+    // Distinct edges are numbered by a scan of first-of-run flags (duplicates stay in place).
+    uint32_t* first_scan = reinterpret_cast<uint32_t*>(t.keys_a);
+    {
+        auto flags = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
+                                                      FirstOfRun{t.keys_b, sentinel});
+        tmp = t.sort_tmp_bytes;
+        TC_TRY(rocprim::inclusive_scan(t.sort_tmp, tmp, flags, first_scan, (size_t)m_in, rocprim::plus<uint32_t>(),
+                                       stream));
+    }
+    hipLaunchKernelGGL(k_set_m, dim3(1), dim3(1), 0, stream, first_scan, m_in, g.meta);
     TC_TRY(hipGetLastError());
 
     // 3: degree (from runs of the lower and of the sorted upper endpoints), rank in (degree, id)
     // order (stable sort keeps ids ascending among equal degrees).
     {
-        uint32_t* up_a = reinterpret_cast<uint32_t*>(t.keys_b);
-        uint32_t* up_b = up_a + m_in;
-        hipLaunchKernelGGL(k_upper, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta, up_a);
+        uint32_t* up_a = t.aux;
+        uint32_t* up_b = t.aux + m_in;
+        hipLaunchKernelGGL(k_upper, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_b, nb, m_in, sentinel,
+                           up_a);
         TC_TRY(hipGetLastError());
         tmp = t.sort_tmp_bytes;
         TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, up_a, up_b, (size_t)m_in, 0, nb < 32 ? nb + 1 : 32, stream));
-        hipLaunchKernelGGL(k_degree, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, up_b, nb, m_in,
-                           g.meta, t.deg);
+        hipLaunchKernelGGL(k_degree, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_b, first_scan, up_b, nb,
+                           m_in, sentinel, g.meta, t.deg);
         TC_TRY(hipGetLastError());
     }
     uint32_t deg_bits = 1;
@@ -354,12 +401,14 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     // 4-5: orientation and CSR in rank space.
     if (!caps.scatter_csr) {
         // Sort the oriented keys: rows come out contiguous and each list sorted by rank.
-        hipLaunchKernelGGL(k_orient_keys, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta,
-                           g.rank, sentinel, t.keys_b);
+        unsigned long long* okeys = t.keys_a;
+        unsigned long long* osorted = reinterpret_cast<unsigned long long*>(t.aux);
+        hipLaunchKernelGGL(k_orient_keys, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_b, nb, m_in, g.rank,
+                           sentinel, okeys);
         TC_TRY(hipGetLastError());
         tmp = t.sort_tmp_bytes;
-        TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, t.keys_b, t.keys_a, (size_t)m_in, 0, 2 * nb, stream));
-        hipLaunchKernelGGL(k_csr_runs, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in, g.meta,
+        TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, okeys, osorted, (size_t)m_in, 0, 2 * nb, stream));
+        hipLaunchKernelGGL(k_csr_runs, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, osorted, nb, m_in, g.meta,
                            t.dplus, g.col);
         TC_TRY(hipGetLastError());
         tmp = t.sort_tmp_bytes;
@@ -367,20 +416,28 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
                                        rocprim::plus<unsigned long long>(), stream));
     } else {
         // Counting sort: out-degrees, offsets, then an atomic scatter (list order unspecified).
-        hipLaunchKernelGGL(k_orient_count, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in,
-                           g.meta, g.rank, t.dplus);
+        hipLaunchKernelGGL(k_orient_count, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_b, nb, m_in,
+                           sentinel, g.rank, t.dplus);
         TC_TRY(hipGetLastError());
         tmp = t.sort_tmp_bytes;
         TC_TRY(rocprim::exclusive_scan(t.sort_tmp, tmp, t.dplus, g.off, (unsigned long long)0, (size_t)n + 1,
                                        rocprim::plus<unsigned long long>(), stream));
         TC_TRY(fill_u32(t.deg, 0, (size_t)n + 1, stream));
-        hipLaunchKernelGGL(k_orient_fill, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_a, nb, m_in,
-                           g.meta, g.rank, g.off, t.deg, g.col);
+        hipLaunchKernelGGL(k_orient_fill, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_b, nb, m_in,
+                           sentinel, g.rank, g.off, t.deg, g.col);
         TC_TRY(hipGetLastError());
     }
 
-    // 6: bins and largest-work-first order.
-    hipLaunchKernelGGL(k_schedule, dim3(grid_for(n)), dim3(kThreads), 0, stream, g.off, g.col, n, caps, g.meta,
+    // 6: bins and largest-work-first order; W(u) from a scan of d+(col[e]).
+    unsigned long long* wscan = reinterpret_cast<unsigned long long*>(t.keys_a);
+    {
+        auto heads = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
+                                                      HeadOutDegree{g.col, t.dplus, g.meta});
+        tmp = t.sort_tmp_bytes;
+        TC_TRY(rocprim::inclusive_scan(t.sort_tmp, tmp, heads, wscan, (size_t)m_in,
+                                       rocprim::plus<unsigned long long>(), stream));
+    }
+    hipLaunchKernelGGL(k_schedule, dim3(grid_for(n)), dim3(kThreads), 0, stream, g.off, wscan, n, caps, g.meta,
                        t.skey_a);
     TC_TRY(hipGetLastError());
     tmp = t.sort_tmp_bytes;

@@ -59,9 +59,9 @@ def kernel_source_sha1() -> str:
     return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
 
 
-def measured_traffic(per_vertex: bool):
+def measured_traffic(per_vertex: bool, workload: str):
     """DRAM-side bytes per count launch from the committed PMC summary, if it
-    was taken on the current kernel source and mode; else None."""
+    was taken on the current kernel source, workload and mode; else None."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     kv = {}
@@ -72,6 +72,8 @@ def measured_traffic(per_vertex: bool):
     if kv.get("kernel_source_sha1") != kernel_source_sha1():
         return None
     if kv.get("per_vertex", "").lower() != str(per_vertex).lower():
+        return None
+    if kv.get("workload") != workload:
         return None
     try:
         return int(kv["traffic_bytes_per_launch"])
@@ -345,7 +347,7 @@ def main():
         "count_only_teps": info.m / (kernel_ms * 1e-3),
         "build_ms": float(np.mean(build_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_vertex),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_vertex, args.workload),
                      "kernel": "tc_count_kernel", "algorithmic_bytes": b_alg,
                      "kernel_source_sha1": kernel_source_sha1()},
     }

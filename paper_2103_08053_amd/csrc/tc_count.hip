@@ -526,7 +526,7 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
 }
 
 template <int S, bool PV, int HK>
-__global__ void __launch_bounds__(1024) tc_count_kernel(CountArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) tc_count_kernel(CountArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t s_wsum[kMaxWaves];
     __shared__ unsigned long long s_acc[kMaxWaves];

@@ -251,6 +251,9 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
     if (threadIdx.x == 0) { s_w = 0; s_max = 0; s_bins[0] = s_bins[1] = s_bins[2] = s_bins[3] = 0; }
     __syncthreads();
     const unsigned long long kWorkMax = (1ull << 40) - 1;
+    // Per-thread partials, reduced across the wave, then one LDS atomic per wave.
+    unsigned long long wsum = 0;
+    uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         const int64_t b = off[r], e = off[r + 1];
         const uint32_t d = (uint32_t)(e - b);
@@ -262,9 +265,29 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         else bin = 2;
         const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
         skey[r] = ((unsigned long long)bin << 40) | (caps.lpt ? (kWorkMax - wk) : 0ull);
-        atomicAdd(&s_w, w);
-        atomicMax(&s_max, d);
-        atomicAdd(&s_bins[bin], 1u);
+        wsum += w;
+        dmax = d > dmax ? d : dmax;
+        nb0 += bin == 0;
+        nb1 += bin == 1;
+        nb2 += bin == 2;
+        nb3 += bin == 3;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        wsum += __shfl_xor(wsum, o);
+        const uint32_t dm = __shfl_xor(dmax, o);
+        dmax = dm > dmax ? dm : dmax;
+        nb0 += __shfl_xor(nb0, o);
+        nb1 += __shfl_xor(nb1, o);
+        nb2 += __shfl_xor(nb2, o);
+        nb3 += __shfl_xor(nb3, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&s_w, wsum);
+        atomicMax(&s_max, dmax);
+        atomicAdd(&s_bins[0], nb0);
+        atomicAdd(&s_bins[1], nb1);
+        atomicAdd(&s_bins[2], nb2);
+        atomicAdd(&s_bins[3], nb3);
     }
     __syncthreads();
     if (threadIdx.x == 0) {

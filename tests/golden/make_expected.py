@@ -4,7 +4,7 @@ Every value in that file comes from ``oracle`` run on inputs from
 ``graphgen``; nothing is taken from the device path.  Re-run after any change
 to the generators or to the oracle's arithmetic:
 
-    python tests/golden/make_expected.py [--large]
+    python tests/golden/make_expected.py [--large] [--huge]
 
 Stored per workload: the total, the cleaned edge count m, W+ (the total
 number of 2-hop probes), the largest out-degree, a checksum of the whole
@@ -53,11 +53,21 @@ def record(g, sample=512, seed=1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--large", action="store_true", help="also the R-MAT scale 22 workload")
+    ap.add_argument("--huge", action="store_true",
+                    help="also the single large instances: R-MAT scale 26 and Erdos-Renyi n = 2^25")
+    ap.add_argument("--keep", action="store_true", help="keep large-instance values already stored")
     args = ap.parse_args()
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     data["rmat16"] = record(W.small_rmat())
     if args.large:
         data["rmat22"] = record(W.large_rmat())
+    if args.huge:
+        for name, fn in (("er25", W.uniform_er), ("rmat26", W.huge_rmat)):
+            if args.keep and name in data:
+                continue
+            data[name] = record(fn())
+            json.dump(data, open(OUT, "w"), indent=1)
+            print(name, data[name]["total"], data[name]["oracle_seconds"], flush=True)
     json.dump(data, open(OUT, "w"), indent=1)
     print({k: (v["total"], v["oracle_seconds"]) for k, v in data.items()})
 

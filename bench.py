@@ -341,7 +341,8 @@ def main():
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "m_in": g.m_in, "m": info.m, "wedges_plus": info.wedges_plus,
                    "max_dplus": info.max_dplus, "per_vertex": per_vertex, "triangles": total,
-                   "bins": {"hub": info.n_hub, "workgroup": info.n_wg, "wavefront": info.n_wave},
+                   "bins": {"global_table": info.n_hub, "large_lds": info.n_big, "workgroup": info.n_wg,
+                            "wavefront": info.n_wave},
                    "params": vars(ctx.params)},
         "count_kernel_ms": kernel_ms,
         "count_only_teps": info.m / (kernel_ms * 1e-3),

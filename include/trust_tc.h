@@ -66,10 +66,11 @@ typedef struct tc_params {
 
 #define TC_F_NO_LPT     0x1u    /* keep rank order instead of largest-work-first within each bin */
 #define TC_F_FORCE_WG   0x2u    /* every vertex goes to the workgroup bin (tests) */
-#define TC_F_FORCE_HUB  0x4u    /* every vertex goes to the global-memory table path (tests) */
+#define TC_F_FORCE_HUB  0x4u    /* every vertex goes to the global-memory table bin (tests) */
 #define TC_F_SCATTER_CSR 0x8u   /* build the CSR by an atomic counting sort (lists unordered) instead of
                                    the default radix sort of the oriented edges (lists sorted by rank) */
 #define TC_F_WIDE_ADDR  0x10u   /* 64-bit list addressing even below 2^30 edges (tests) */
+#define TC_F_FORCE_BIG  0x20u   /* every vertex goes to the large-LDS-table bin (tests) */
 
 /* Opaque handles. */
 typedef struct tc_context tc_context;
@@ -81,11 +82,13 @@ typedef struct tc_graph_info {
     uint64_t m;           /* undirected edges after cleaning = oriented edges */
     uint64_t wedges_plus; /* W+ = sum over oriented (u,v) of d+(v): the number of 2-hop probes */
     uint32_t max_dplus;   /* largest out-degree */
-    uint32_t n_hub;       /* vertices in the global-memory table bin */
+    uint32_t n_hub;       /* vertices in the global-memory table bin (too large for any LDS table) */
     uint32_t n_wg;        /* vertices in the workgroup (LDS) bin */
     uint32_t n_wave;      /* vertices in the wavefront (LDS) bin */
     uint32_t wave_cap;    /* out-degree limits used for the bins */
     uint32_t wg_cap;
+    uint32_t n_big;       /* vertices in the large-LDS bin (one workgroup per CU with all of its LDS) */
+    uint32_t big_cap;     /* out-degree limit of the large-LDS bin */
 } tc_graph_info;
 
 /* Fill *p with the default knobs (struct_size set). */
@@ -138,7 +141,9 @@ tc_status tc_count_scratch_bytes(const tc_context* ctx, uint32_t n, uint64_t m_i
 
 /* Count the triangles of a built graph.  Asynchronous: the total is written
  * to d_total (device uint64); d_per_vertex as in tc_count.  This call is one
- * persistent kernel launch plus, with d_per_vertex, one gather launch. */
+ * persistent kernel launch (preceded, when some out-degree may exceed the
+ * workgroup bin's limit, by one launch for the large-vertex bins) plus, with
+ * d_per_vertex, one gather launch. */
 tc_status tc_graph_count(tc_context* ctx, const tc_graph* g, uint64_t* d_total,
                          uint64_t* d_per_vertex, void* d_scratch, uint64_t scratch_bytes,
                          void* stream);
@@ -193,7 +198,7 @@ tc_status tc_graph_k(const tc_graph* g, uint32_t* k);
  * HIP events on its stream around its device steps (events owned by ctx).
  * tc_timing_last waits for the last recorded events and returns, in
  * milliseconds, the last build (clean, orient, CSR, bins) and the last count
- * kernel launch alone; a value is -1 if that step has not run since timing
+ * kernel launches alone (large-vertex and main kernel); a value is -1 if that step has not run since timing
  * was switched on. */
 tc_status tc_timing_enable(tc_context* ctx, int on);
 tc_status tc_timing_last(tc_context* ctx, float* build_ms, float* count_kernel_ms);

@@ -17,6 +17,7 @@ struct tc_context {
     int device = 0;
     int cu_count = 0;
     size_t lds_per_block_max = 0;
+    uint32_t big_lds_bytes = 0;  // dynamic LDS of the large-vertex kernel: all a workgroup may have
     tc_params p{};
     std::string err;
     bool timing = false;
@@ -24,7 +25,7 @@ struct tc_context {
     bool have_build = false, have_count = false;
     hipStream_t capture_stream = nullptr;  // for tc_graph_count_replay
     struct Occ {
-        uint32_t S, pv, hk, threads, lds;
+        uint32_t hub, S, pv, hk, threads, lds;
         int per_cu;
     };
     std::vector<Occ> occ;  // resident workgroups per CU, by kernel variant and launch shape
@@ -84,7 +85,8 @@ tc_status check_params(const tc_params* p) {
     if (p->load_factor_pct < 10 || p->load_factor_pct > 100) return TC_E_INVALID;
     if (p->hash_kind > 1) return TC_E_INVALID;
     if (p->light_chunk < 1 || p->light_chunk > 256) return TC_E_INVALID;
-    if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SCATTER_CSR | TC_F_WIDE_ADDR))
+    if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SCATTER_CSR | TC_F_WIDE_ADDR |
+                     TC_F_FORCE_BIG))
         return TC_E_INVALID;
     return TC_OK;
 }
@@ -93,14 +95,17 @@ uint32_t slice_words(const tc_params& p) {
     return (p.wg_lds_bytes / 4 / p.wg_waves) & ~3u;
 }
 
-tc::BinCaps bin_caps(const tc_params& p) {
+tc::BinCaps bin_caps(const tc_context* ctx, const tc_params& p) {
     tc::BinCaps c{};
     // Capacities assume the per-vertex layout (the larger one), so one binning serves both modes.
     c.wg_cap = tc::capacity(p.wg_lds_bytes / 4, p.slots_per_bucket, p.load_factor_pct, true);
     c.wave_cap = tc::capacity(slice_words(p), p.slots_per_bucket, p.load_factor_pct, true);
     if (p.wave_max_dplus && p.wave_max_dplus < c.wave_cap) c.wave_cap = p.wave_max_dplus;
+    c.big_cap = tc::capacity(ctx->big_lds_bytes / 4, p.slots_per_bucket, p.load_factor_pct, true);
+    if (c.big_cap < c.wg_cap) c.big_cap = c.wg_cap;
     c.force_wg = (p.flags & TC_F_FORCE_WG) != 0;
     c.force_hub = (p.flags & TC_F_FORCE_HUB) != 0;
+    c.force_big = (p.flags & TC_F_FORCE_BIG) != 0;
     c.lpt = (p.flags & TC_F_NO_LPT) == 0;
     c.scatter_csr = (p.flags & TC_F_SCATTER_CSR) != 0;
     return c;
@@ -199,7 +204,7 @@ tc_status build_into(tc_context* ctx, tc_graph* g, uint32_t n, uint64_t m_in, co
     g->batch = batch != nullptr;
     g->k = batch ? batch->k : 1;
     g->p = ctx->p;
-    g->caps = bin_caps(ctx->p);
+    g->caps = bin_caps(ctx, ctx->p);
     g->empty = (n == 0 || m_in == 0);
     if (g->empty) {
         g->dev = tc::GraphDev{};
@@ -222,20 +227,32 @@ tc_status build_into(tc_context* ctx, tc_graph* g, uint32_t n, uint64_t m_in, co
     return TC_OK;
 }
 
-tc_status occupancy(tc_context* ctx, const tc_params& p, bool pv, int* per_cu) {
-    const uint32_t threads = 64 * p.wg_waves;
+// Launch shape of the main kernel (workgroups of wg_waves wavefronts, wg_lds_bytes of LDS) or of the
+// large-vertex kernel (16 wavefronts, all the LDS a workgroup may have).
+uint32_t launch_threads(const tc_params& p, bool hub) { return hub ? 64 * tc::kMaxWaves : 64 * p.wg_waves; }
+uint32_t launch_lds(const tc_context* ctx, const tc_params& p, bool hub) {
+    return hub ? ctx->big_lds_bytes : p.wg_lds_bytes;
+}
+
+tc_status occupancy(tc_context* ctx, const tc_params& p, bool pv, bool hub, int* per_cu) {
+    const uint32_t threads = launch_threads(p, hub), lds = launch_lds(ctx, p, hub);
     for (const auto& o : ctx->occ)
-        if (o.S == p.slots_per_bucket && o.pv == (uint32_t)pv && o.hk == p.hash_kind && o.threads == threads &&
-            o.lds == p.wg_lds_bytes) {
+        if (o.hub == (uint32_t)hub && o.S == p.slots_per_bucket && o.pv == (uint32_t)pv && o.hk == p.hash_kind &&
+            o.threads == threads && o.lds == lds) {
             *per_cu = o.per_cu;
             return TC_OK;
         }
     int q = 0;
-    HIP_TRY(ctx, tc::count_kernel_info(p.slots_per_bucket, pv, p.hash_kind, threads, p.wg_lds_bytes, &q));
-    if (q < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, p.wg_lds_bytes);
-    ctx->occ.push_back({p.slots_per_bucket, (uint32_t)pv, p.hash_kind, threads, p.wg_lds_bytes, q});
+    HIP_TRY(ctx, tc::count_kernel_info(hub, p.slots_per_bucket, pv, p.hash_kind, threads, lds, &q));
+    if (q < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, lds);
+    ctx->occ.push_back({(uint32_t)hub, p.slots_per_bucket, (uint32_t)pv, p.hash_kind, threads, lds, q});
     *per_cu = q;
     return TC_OK;
+}
+
+// Whether any vertex can land in bins 0 or 1 (those need the large-vertex launch).
+bool needs_hub_launch(const tc_graph* g) {
+    return g->caps.force_hub || g->caps.force_big || dplus_bound(g->n, g->m_in) > g->caps.wg_cap;
 }
 
 // The count: clears, the persistent kernel and (per-vertex mode) the gather.
@@ -264,21 +281,30 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.hub_words = L.hub_words;
     a.hub_wgs = L.hub_wgs;
     a.slice_words = slice_words(p);
-    a.table_words = p.wg_lds_bytes / 4;
     a.load_pct = p.load_factor_pct;
     a.chunk = p.light_chunk;
     a.wide = (g->m_in >= (1ull << 30)) || (p.flags & TC_F_WIDE_ADDR) ? 1u : 0u;
-    const uint32_t threads = 64 * p.wg_waves;
-    int per_cu = 0;
-    if (tc_status st = occupancy(ctx, p, pv, &per_cu)) return st;
-    uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu * ctx->cu_count);
-    if (grid < a.hub_wgs) a.hub_wgs = grid;
+    const bool hub = needs_hub_launch(g);
+    int per_cu = 0, per_cu_hub = 0;
+    if (tc_status st = occupancy(ctx, p, pv, false, &per_cu)) return st;
+    if (hub)
+        if (tc_status st = occupancy(ctx, p, pv, true, &per_cu_hub)) return st;
+    const uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu * ctx->cu_count);
+    const uint32_t grid_hub = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu_hub * ctx->cu_count);
+    if (grid_hub < a.hub_wgs) a.hub_wgs = grid_hub;
     HIP_TRY(ctx, tc::fill_u32(a.heads, 0, 4, s));
     HIP_TRY(ctx, tc::fill_u32(d_totals, 0, 2 * (size_t)g->k, s));
     if (pv) HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * (size_t)g->n, s));
     const bool rec = record && ctx->timing;
     if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
-    HIP_TRY(ctx, tc::count_launch(p.slots_per_bucket, pv, p.hash_kind, grid, threads, p.wg_lds_bytes, a, s));
+    if (hub) {
+        a.table_words = launch_lds(ctx, p, true) / 4;
+        HIP_TRY(ctx, tc::count_launch(true, p.slots_per_bucket, pv, p.hash_kind, grid_hub, launch_threads(p, true),
+                                      launch_lds(ctx, p, true), a, s));
+    }
+    a.table_words = p.wg_lds_bytes / 4;
+    HIP_TRY(ctx, tc::count_launch(false, p.slots_per_bucket, pv, p.hash_kind, grid, launch_threads(p, false),
+                                  p.wg_lds_bytes, a, s));
     if (rec) {
         HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
         ctx->have_count = true;
@@ -345,7 +371,18 @@ tc_status tc_create(int hip_device, const tc_params* p, tc_context** out) {
     if (!c) return TC_E_NOMEM;
     c->device = hip_device;
     c->cu_count = prop.multiProcessorCount;
-    c->lds_per_block_max = prop.sharedMemPerBlock;
+    // LDS a workgroup may use: the opt-in limit (past 64 KB needs hipFuncSetAttribute), within one CU's LDS.
+    c->lds_per_block_max = std::max(prop.sharedMemPerBlock, prop.sharedMemPerBlockOptin);
+    if (prop.maxSharedMemoryPerMultiProcessor)
+        c->lds_per_block_max = std::min(c->lds_per_block_max, prop.maxSharedMemoryPerMultiProcessor);
+    {
+        uint32_t static_lds = 0;
+        if (hipSetDevice(hip_device) != hipSuccess || tc::count_kernel_static_lds(&static_lds) != hipSuccess) {
+            delete c;
+            return TC_E_DEVICE;
+        }
+        c->big_lds_bytes = (uint32_t)((c->lds_per_block_max - static_lds) & ~(size_t)15);
+    }
     c->p = q;
     *out = c;
     return TC_OK;
@@ -491,6 +528,7 @@ tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out)
     out->n = g->n;
     out->wave_cap = g->caps.wave_cap;
     out->wg_cap = g->caps.wg_cap;
+    out->big_cap = g->caps.big_cap;
     if (g->empty) return TC_OK;
     tc::GraphMeta m;
     if (hipSetDevice(g->ctx->device) != hipSuccess) return TC_E_DEVICE;
@@ -501,8 +539,9 @@ tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out)
     out->wedges_plus = m.wplus;
     out->max_dplus = m.max_dplus;
     out->n_hub = m.bins[0];
-    out->n_wg = m.bins[1];
-    out->n_wave = m.bins[2];
+    out->n_big = m.bins[1];
+    out->n_wg = m.bins[2];
+    out->n_wave = m.bins[3];
     if (m.err & 1u) return TC_E_RANGE;
     return TC_OK;
 }
@@ -576,8 +615,11 @@ tc_status tc_graph_count_replay(tc_context* ctx, tc_graph* g, uint64_t* d_totals
         drop_capture(g);
         if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
         int per_cu = 0;  // resolve launch shapes before capture (no attribute calls while capturing)
-        if (!g->empty)
-            if (tc_status st = occupancy(ctx, g->p, d_per_vertex != nullptr, &per_cu)) return st;
+        if (!g->empty) {
+            if (tc_status st = occupancy(ctx, g->p, d_per_vertex != nullptr, false, &per_cu)) return st;
+            if (needs_hub_launch(g))
+                if (tc_status st = occupancy(ctx, g->p, d_per_vertex != nullptr, true, &per_cu)) return st;
+        }
         HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
         tc_status st = count_into(ctx, g, d_totals, d_per_vertex, d_scratch, L, ctx->capture_stream, false);
         hipGraph_t hg = nullptr;

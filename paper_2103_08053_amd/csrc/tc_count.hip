@@ -525,17 +525,33 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
     group_sync<WG>();  // the table memory is reused by the next vertex
 }
 
+// Sum of the workgroup's per-wavefront totals, one atomic per workgroup.
+__device__ __forceinline__ void add_workgroup_total(const CountArgs& a, unsigned long long acc,
+                                                    unsigned long long* s_acc, int tid, int lane, int wave, int nw) {
+    if (lane == 0) s_acc[wave] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long sum = 0;
+        for (int w = 0; w < nw; ++w) sum += s_acc[w];
+        if (sum && a.total) atomicAdd(a.total, sum);
+    }
+}
+
+// Large vertices (bins 0 and 1), launched before the main kernel with one
+// workgroup per CU and the whole LDS: bin 1 tables fill the workgroup's LDS;
+// bin 0 tables (too large for any LDS) live in global memory, one region per
+// participating workgroup (the first hub_wgs workgroups).
 template <int S, bool PV, int HK>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) tc_count_kernel(CountArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) tc_hub_kernel(CountArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t s_wsum[kMaxWaves];
     __shared__ unsigned long long s_acc[kMaxWaves];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     unsigned long long acc = 0;
-    const uint32_t n_hub = a.meta->bins[0], n_wg = a.meta->bins[1], n_wave = a.meta->bins[2];
+    const uint32_t n_hub = a.meta->bins[0], n_big = a.meta->bins[1];
+    if (n_hub + n_big == 0) return;
 
-    // Hub bin: global-memory tables, one region per participating workgroup.
     if (blockIdx.x < a.hub_wgs && n_hub) {
         uint32_t* gt = a.hub_scratch + (size_t)blockIdx.x * a.hub_words;
         for (;;) {
@@ -547,25 +563,50 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             process<S, PV, HK, true, false>(a, a.items[j], gt, a.hub_words, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
         }
     }
-    // Workgroup bin: the table fills the workgroup's LDS.
-    if (n_wg) {
+    if (n_big) {
         for (;;) {
             if (tid == 0) s_item = atomicAdd(&a.heads[1], 1u);
             __syncthreads();
             const uint32_t j = s_item;
             __syncthreads();
+            if (j >= n_big) break;
+            process<S, PV, HK, true, true>(a, a.items[n_hub + j], lds, a.table_words, tid, blockDim.x, wave, nw, lane,
+                                           s_wsum, acc);
+        }
+    }
+    add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);
+}
+
+// Everything else (bins 2 and 3): a persistent grid filling the GPU.
+template <int S, bool PV, int HK>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) tc_count_kernel(CountArgs a) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ uint32_t s_wsum[kMaxWaves];
+    __shared__ unsigned long long s_acc[kMaxWaves];
+    __shared__ uint32_t s_item;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    unsigned long long acc = 0;
+    const uint32_t n_before = a.meta->bins[0] + a.meta->bins[1], n_wg = a.meta->bins[2], n_wave = a.meta->bins[3];
+
+    // Workgroup bin: the table fills the workgroup's LDS.
+    if (n_wg) {
+        for (;;) {
+            if (tid == 0) s_item = atomicAdd(&a.heads[2], 1u);
+            __syncthreads();
+            const uint32_t j = s_item;
+            __syncthreads();
             if (j >= n_wg) break;
-            process<S, PV, HK, true, true>(a, a.items[n_hub + j], lds, a.table_words, tid, blockDim.x, wave, nw, lane, s_wsum,
-                                           acc);
+            process<S, PV, HK, true, true>(a, a.items[n_before + j], lds, a.table_words, tid, blockDim.x, wave, nw, lane,
+                                           s_wsum, acc);
         }
     }
     // Wavefront bin: each wavefront owns a slice of the LDS.
     {
         uint32_t* slice = lds + (size_t)wave * a.slice_words;
-        const uint32_t base = n_hub + n_wg;
+        const uint32_t base = n_before + n_wg;
         for (;;) {
             uint32_t j0 = 0;
-            if (lane == 0) j0 = atomicAdd(&a.heads[2], a.chunk);
+            if (lane == 0) j0 = atomicAdd(&a.heads[3], a.chunk);
             j0 = __builtin_amdgcn_readfirstlane(j0);
             if (j0 >= n_wave) break;
             const uint32_t j1 = (j0 + a.chunk < n_wave) ? j0 + a.chunk : n_wave;
@@ -573,38 +614,41 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 process<S, PV, HK, false, true>(a, a.items[base + j], slice, a.slice_words, lane, 64, 0, 1, lane, nullptr, acc);
         }
     }
-
-    if (lane == 0) s_acc[wave] = acc;
-    __syncthreads();
-    if (tid == 0) {
-        unsigned long long sum = 0;
-        for (int w = 0; w < nw; ++w) sum += s_acc[w];
-        if (sum && a.total) atomicAdd(a.total, sum);
-    }
+    add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);
 }
 
 typedef void (*KernelFn)(CountArgs);
 
-template <int S>
+template <int S, bool HUB>
 KernelFn pick_hk(bool pv, uint32_t hk) {
-    if (pv) return hk ? tc_count_kernel<S, true, 1> : tc_count_kernel<S, true, 0>;
-    return hk ? tc_count_kernel<S, false, 1> : tc_count_kernel<S, false, 0>;
+    if constexpr (HUB) {
+        if (pv) return hk ? tc_hub_kernel<S, true, 1> : tc_hub_kernel<S, true, 0>;
+        return hk ? tc_hub_kernel<S, false, 1> : tc_hub_kernel<S, false, 0>;
+    } else {
+        if (pv) return hk ? tc_count_kernel<S, true, 1> : tc_count_kernel<S, true, 0>;
+        return hk ? tc_count_kernel<S, false, 1> : tc_count_kernel<S, false, 0>;
+    }
 }
 
+template <bool HUB>
 KernelFn pick(uint32_t S, bool pv, uint32_t hk) {
     switch (S) {
-        case 1: return pick_hk<1>(pv, hk);
-        case 2: return pick_hk<2>(pv, hk);
-        case 4: return pick_hk<4>(pv, hk);
+        case 1: return pick_hk<1, HUB>(pv, hk);
+        case 2: return pick_hk<2, HUB>(pv, hk);
+        case 4: return pick_hk<4, HUB>(pv, hk);
         default: return nullptr;
     }
 }
 
+KernelFn pick_kernel(bool hub, uint32_t S, bool pv, uint32_t hk) {
+    return hub ? pick<true>(S, pv, hk) : pick<false>(S, pv, hk);
+}
+
 }  // namespace
 
-hipError_t count_kernel_info(uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads, uint32_t lds_bytes,
+hipError_t count_kernel_info(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads, uint32_t lds_bytes,
                              int* blocks_per_cu) {
-    KernelFn f = pick(S, pv, hash_kind);
+    KernelFn f = pick_kernel(hub, S, pv, hash_kind);
     if (!f) return hipErrorInvalidValue;
     if (lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(f),
@@ -615,9 +659,16 @@ hipError_t count_kernel_info(uint32_t S, bool pv, uint32_t hash_kind, uint32_t t
                                                         (int)threads, (size_t)lds_bytes);
 }
 
-hipError_t count_launch(uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
+hipError_t count_kernel_static_lds(uint32_t* bytes) {
+    hipFuncAttributes attr{};
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(pick_kernel(true, 4, true, 0)));
+    if (e == hipSuccess) *bytes = (uint32_t)attr.sharedSizeBytes;
+    return e;
+}
+
+hipError_t count_launch(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
                         uint32_t lds_bytes, const CountArgs& a, hipStream_t stream) {
-    KernelFn f = pick(S, pv, hash_kind);
+    KernelFn f = pick_kernel(hub, S, pv, hash_kind);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(grid), dim3(threads), lds_bytes, stream, a);
     return hipGetLastError();

@@ -20,8 +20,10 @@ struct GraphMeta {
     unsigned int reserved0;
     unsigned int max_dplus;
     unsigned int err;               // bit 0: some input id >= n
-    unsigned int bins[4];           // vertex counts: hub, workgroup, wavefront, skipped (d+ < 2 or no 2-hop work)
-    unsigned int pad[53];
+    // vertex counts: global-memory tables, large LDS tables (one workgroup per CU), workgroup LDS
+    // tables, wavefront LDS slices, skipped (d+ < 2 or no 2-hop work)
+    unsigned int bins[5];
+    unsigned int pad[52];
 };
 static_assert(sizeof(GraphMeta) == 256, "meta is one 256-byte block");
 
@@ -119,8 +121,8 @@ struct BuildTemp {
 };
 
 struct BinCaps {
-    uint32_t wave_cap, wg_cap;
-    bool force_wg, force_hub, lpt, scatter_csr;
+    uint32_t wave_cap, wg_cap, big_cap;
+    bool force_wg, force_hub, force_big, lpt, scatter_csr;
 };
 
 struct Layout {
@@ -141,16 +143,16 @@ struct CountArgs {
     const int64_t* off;
     const uint32_t* col;
     const uint32_t* items;
-    uint32_t* heads;                 // [4] queue heads (zeroed before launch)
+    uint32_t* heads;                 // [4] queue heads, one per bin (zeroed before the launches)
     unsigned long long* total;       // [1] (zeroed before launch); single-graph mode
     const uint32_t* gid;             // [n] graph of each rank (batch mode), or null
     unsigned long long* totals;      // [k] per-graph totals (batch mode, zeroed before launch)
     unsigned long long* tv;          // [n] per-vertex counts in rank space, or null
     uint32_t* hub_scratch;           // hub_wgs * hub_words words
     unsigned long long hub_words;
-    uint32_t hub_wgs;
+    uint32_t hub_wgs;                // workgroups of the large-table launch that take global-table vertices
     uint32_t slice_words;            // per-wavefront LDS slice
-    uint32_t table_words;            // LDS words of the workgroup table region
+    uint32_t table_words;            // LDS words of the workgroup table region (of this launch)
     uint32_t load_pct;
     uint32_t chunk;
     uint32_t wide;                   // col spans 4 GiB or more: 64-bit addressing in the probe
@@ -165,10 +167,11 @@ hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream);
 hipError_t gather_per_vertex(const unsigned long long* tv_rank, const uint32_t* rank, uint32_t n,
                              unsigned long long* out, hipStream_t stream);
 
-// tc_count.hip
-hipError_t count_kernel_info(uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
+// tc_count.hip.  `hub` selects the large-vertex kernel (bins 0 and 1) instead of the main one.
+hipError_t count_kernel_info(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
                              uint32_t lds_bytes, int* blocks_per_cu);
-hipError_t count_launch(uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
+hipError_t count_kernel_static_lds(uint32_t* bytes);
+hipError_t count_launch(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
                         uint32_t lds_bytes, const CountArgs& a, hipStream_t stream);
 
 }  // namespace tc

@@ -243,26 +243,29 @@ __global__ void k_csr_runs(const unsigned long long* __restrict__ okeys, uint32_
 
 // One thread per vertex: d+, W(u) = sum of d+(v) over v in N+(u) (from the
 // inclusive scan of d+(col[e]) over the edges), bin, and the sort key
-// (bin << 40 | reversed work).
+// (bin << 40 | reversed work).  Bins: 0 global-memory table (too large for
+// any LDS table), 1 large LDS table (whole LDS of a workgroup, one per CU),
+// 2 workgroup LDS table, 3 wavefront LDS slice, 4 skipped.
 __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long long* __restrict__ wscan, uint32_t n,
                            BinCaps caps, GraphMeta* meta, unsigned long long* __restrict__ skey) {
     __shared__ unsigned long long s_w;
-    __shared__ unsigned int s_max, s_bins[4];
-    if (threadIdx.x == 0) { s_w = 0; s_max = 0; s_bins[0] = s_bins[1] = s_bins[2] = s_bins[3] = 0; }
+    __shared__ unsigned int s_max, s_bins[5];
+    if (threadIdx.x == 0) { s_w = 0; s_max = 0; s_bins[0] = s_bins[1] = s_bins[2] = s_bins[3] = s_bins[4] = 0; }
     __syncthreads();
     const unsigned long long kWorkMax = (1ull << 40) - 1;
     // Per-thread partials, reduced across the wave, then one LDS atomic per wave.
     unsigned long long wsum = 0;
-    uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0;
+    uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         const int64_t b = off[r], e = off[r + 1];
         const uint32_t d = (uint32_t)(e - b);
         const unsigned long long w = d ? wscan[e - 1] - (b ? wscan[b - 1] : 0ull) : 0ull;
         uint32_t bin;
-        if (d < 2 || w == 0) bin = 3;
-        else if (caps.force_hub || d > caps.wg_cap) bin = 0;
-        else if (caps.force_wg || d > caps.wave_cap) bin = 1;
-        else bin = 2;
+        if (d < 2 || w == 0) bin = 4;
+        else if (caps.force_hub || d > caps.big_cap) bin = 0;
+        else if (caps.force_big || d > caps.wg_cap) bin = 1;
+        else if (caps.force_wg || d > caps.wave_cap) bin = 2;
+        else bin = 3;
         const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
         skey[r] = ((unsigned long long)bin << 40) | (caps.lpt ? (kWorkMax - wk) : 0ull);
         wsum += w;
@@ -271,6 +274,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         nb1 += bin == 1;
         nb2 += bin == 2;
         nb3 += bin == 3;
+        nb4 += bin == 4;
     }
     for (int o = 32; o > 0; o >>= 1) {
         wsum += __shfl_xor(wsum, o);
@@ -280,6 +284,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         nb1 += __shfl_xor(nb1, o);
         nb2 += __shfl_xor(nb2, o);
         nb3 += __shfl_xor(nb3, o);
+        nb4 += __shfl_xor(nb4, o);
     }
     if ((threadIdx.x & 63) == 0) {
         atomicAdd(&s_w, wsum);
@@ -288,12 +293,13 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         atomicAdd(&s_bins[1], nb1);
         atomicAdd(&s_bins[2], nb2);
         atomicAdd(&s_bins[3], nb3);
+        atomicAdd(&s_bins[4], nb4);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(&meta->wplus, s_w);
         atomicMax(&meta->max_dplus, s_max);
-        for (int i = 0; i < 4; ++i) atomicAdd(&meta->bins[i], s_bins[i]);
+        for (int i = 0; i < 5; ++i) atomicAdd(&meta->bins[i], s_bins[i]);
     }
 }
 
@@ -465,7 +471,7 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     TC_TRY(hipGetLastError());
     tmp = t.sort_tmp_bytes;
     TC_TRY(rocprim::radix_sort_pairs(t.sort_tmp, tmp, t.skey_a, t.skey_b, rocprim::counting_iterator<uint32_t>(0),
-                                     g.items, (size_t)n, 0, 42, stream));
+                                     g.items, (size_t)n, 0, 43, stream));
     return hipSuccess;
 }
 

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(tc._Params) == 10 * 4
-    assert ctypes.sizeof(tc._GraphInfo) == 3 * 8 + 6 * 4
+    assert ctypes.sizeof(tc._GraphInfo) == 3 * 8 + 8 * 4
 
 
 def test_default_params():

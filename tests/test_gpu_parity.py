@@ -105,6 +105,7 @@ def test_rmat_scale16_against_stored(ctx):
 FORCED = [
     dict(flags=2),                              # every vertex in the workgroup bin
     dict(flags=4),                              # every vertex in the global-memory table bin
+    dict(flags=32),                             # every vertex in the large-LDS bin
     dict(wg_lds_bytes=4096, wg_waves=4),        # tiny LDS: most vertices spill to the global-table bin
     dict(slots_per_bucket=1), dict(slots_per_bucket=4),
     dict(load_factor_pct=100), dict(load_factor_pct=10),
@@ -112,7 +113,7 @@ FORCED = [
     dict(slots_per_bucket=1, load_factor_pct=100, flags=4),   # long probe chains in global memory
     dict(hash_kind=1), dict(light_chunk=1), dict(light_chunk=7), dict(flags=1), dict(flags=8),
     dict(wg_waves=1), dict(wg_waves=4), dict(wg_waves=16, wg_lds_bytes=131072),
-    dict(grid_wgs=3), dict(grid_wgs=1, flags=4), dict(wave_max_dplus=8),
+    dict(grid_wgs=3), dict(grid_wgs=1, flags=4), dict(grid_wgs=2, flags=32), dict(wave_max_dplus=8),
     dict(flags=16), dict(flags=16 | 2, slots_per_bucket=1, load_factor_pct=100),   # 64-bit list addressing
 ]
 
@@ -132,14 +133,20 @@ def test_forced_paths_agree(torch, forced_graphs, kw):
 
 
 def test_bins_are_exercised(torch):
-    """A low wavefront cap routes a skewed graph through both LDS bins, and
-    the tiny-LDS parameters route it through the global-table bin."""
+    """A low wavefront cap routes a skewed graph through both LDS bins; the
+    tiny-LDS parameters route its largest vertices to the large-LDS bin (the
+    global-table bin is reached through TC_F_FORCE_HUB in the forced-path
+    cases: no graph the oracle counts quickly has an out-degree beyond the
+    large-LDS limit)."""
     from paper_2103_08053_amd import Context, Params
     g = gg.rmat(14, 16, seed=1)
     info = Context(0, Params(wave_max_dplus=32)).build(g.src, g.dst, g.n).info()
-    assert info.n_wg > 0 and info.n_wave > 0 and info.n_hub == 0
-    small = Context(0, Params(wg_lds_bytes=4096, wg_waves=4)).build(g.src, g.dst, g.n).info()
-    assert small.n_hub > 0
+    assert info.n_wg > 0 and info.n_wave > 0 and info.n_hub == 0 and info.n_big == 0
+    assert info.big_cap > info.wg_cap
+    c = Context(0, Params(wg_lds_bytes=4096, wg_waves=4))
+    small = c.build(g.src, g.dst, g.n).info()
+    assert small.n_big > 0 and small.n_hub == 0
+    assert_parity(c, g)
 
 
 # ----------------------------------------------------------------------------- edge cases

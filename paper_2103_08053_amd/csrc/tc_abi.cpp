@@ -146,10 +146,10 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
 
     o = 0;
     L.c_total = o;  o = align_up(o + 8);
-    L.c_heads = o;  o = align_up(o + 16);
+    L.c_heads = o;  o = align_up(o + 4 * tc::kHeadWords);
     L.c_tv = o;     o = align_up(o + 8 * (size_t)n);
     const uint32_t dmax = dplus_bound(n, m_in);
-    L.hub_words = tc::geometry(dmax, p.slots_per_bucket, p.load_factor_pct, true).words;
+    L.hub_words = tc::geometry(dmax, p.slots_per_bucket, tc::load_recip(p.load_factor_pct), true).words;
     uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)std::max(1, ctx ? ctx->cu_count : 1);
     L.hub_wgs = std::min<uint32_t>(tc::kHubWgs, std::max<uint32_t>(1, grid));
     L.c_hub = o;    o = align_up(o + 4 * L.hub_words * L.hub_wgs);
@@ -281,7 +281,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.hub_words = L.hub_words;
     a.hub_wgs = L.hub_wgs;
     a.slice_words = slice_words(p);
-    a.load_pct = p.load_factor_pct;
+    a.lrecip = tc::load_recip(p.load_factor_pct);
     a.chunk = p.light_chunk;
     a.wide = (g->m_in >= (1ull << 30)) || (p.flags & TC_F_WIDE_ADDR) ? 1u : 0u;
     const bool hub = needs_hub_launch(g);
@@ -292,7 +292,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     const uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu * ctx->cu_count);
     const uint32_t grid_hub = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu_hub * ctx->cu_count);
     if (grid_hub < a.hub_wgs) a.hub_wgs = grid_hub;
-    HIP_TRY(ctx, tc::fill_u32(a.heads, 0, 4, s));
+    HIP_TRY(ctx, tc::fill_u32(a.heads, 0, tc::kHeadWords, s));
     HIP_TRY(ctx, tc::fill_u32(d_totals, 0, 2 * (size_t)g->k, s));
     if (pv) HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * (size_t)g->n, s));
     const bool rec = record && ctx->timing;

@@ -1,11 +1,12 @@
-// The counting kernel: vertex-centric hashing (paper Section 3, Algorithm 1)
+// The counting kernels: vertex-centric hashing (paper Section 3, Algorithm 1)
 // on the oriented rank-space CSR, for gfx950.
 //
-// One persistent launch.  A "group" owns one vertex u at a time:
-//   * hub bin      : the whole workgroup, table in a global-memory region of
-//                    its own (out-degree too large for LDS);
-//   * workgroup bin: the whole workgroup, table in the workgroup's LDS;
-//   * wavefront bin: one 64-lane wavefront, table in its slice of the LDS.
+// Two persistent launches.  A "group" owns one vertex u at a time:
+//   * large-vertex launch (one workgroup of 16 wavefronts per CU, all of its
+//     LDS): bin 0, out-degree too large for any LDS table, table in a
+//     global-memory region of the workgroup; bin 1, table in the LDS;
+//   * main launch: bin 2, the whole workgroup with the table in its LDS;
+//     bin 3, one 64-lane wavefront with the table in its slice of the LDS.
 // This is the degree-aware resource assignment of Section 4.3 (a CTA for
 // large vertices, a warp for small ones; vertices with fewer than two
 // out-neighbours skipped), with atomic dynamic work fetching (one vertex per
@@ -30,17 +31,18 @@
 //            intersection / linearSearch); a hit is one triangle (u, v_k, w).
 //            A lookup that must continue to the next bucket is parked in
 //            registers and resumed with other parked lookups, so chains never
-//            stall a whole wavefront (LDS tables; the global-memory tables of
-//            the hub bin walk chains lane by lane).
-//   reduce : the hit compares are balloted and counted with a popcount on
-//            the scalar unit, accumulated per wavefront, summed across the
-//            workgroup in LDS and added to the total with one atomic per
-//            workgroup at the end.  For a batch of graphs each vertex's hits
-//            go to its graph's total instead.
+//            stall a whole wavefront (LDS tables; the global-memory tables
+//            walk chains lane by lane).
+//   reduce : each lane counts its hits; the wavefront sums them with DPP lane
+//            moves, the workgroup in LDS, and one atomic per workgroup adds
+//            the launch's share to the total.  For a batch of graphs each
+//            vertex's hits go to its graph's total instead.
 // Per-vertex mode adds, per hit, an LDS tally on the matched slot (its
-// element is the triangle's w) and one on v_k; after the probe, u's hits and
-// the non-zero tallies go to the per-vertex array with one global atomic each.
+// element is the triangle's w) and a register tally for v_k (added to an LDS
+// tally when the lane leaves v_k's list); after the probe, u's hits and the
+// non-zero tallies go to the per-vertex array with one global atomic each.
 #include "tc_internal.h"
+#include "tc_wave.h"
 
 namespace tc {
 namespace {
@@ -61,22 +63,6 @@ template <int HK>
 __device__ __forceinline__ uint32_t hash_of(uint32_t w, uint32_t B) {
     if constexpr (HK == 0) return w & (B - 1);
     else return (uint32_t)(((uint64_t)(w * 0x9E3779B1u) * B) >> 32);
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-// Sum of a per-lane value over the wavefront (butterfly of lane swaps).
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return __builtin_amdgcn_readfirstlane(v);
 }
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -351,25 +337,47 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         }
         probe_group(wa, ka);
     }
-    // Leftover full chunks, one at a time.
-    for (; c < nfull; ++c) {
-        uint32_t w, kk = 0;
-        fetch(w, kk);
-        const uint32_t b = hash_of<HK>(w, pr.B);
-        const Bucket<S> v = read_bucket<S>(pr.slots, b);
-        resolve(v, w, b, kk, ~0ull);
-    }
-    // Ragged last chunk: lanes past hi sit out.
-    if (lo + (nfull << 6) < hi) {
-        const bool act = lo + (nfull << 6) + (uint32_t)lane < hi;
-        uint32_t w = 0;
-        if (act) {
-            if (cur >= end) advance();
-            w = load();
+    // Remaining chunks (leftover full ones, then the ragged last one, whose lanes past hi sit out) in
+    // groups of up to kUnroll: every load of a group is issued before the group is probed.
+    uint32_t left = nfull - c + ((lo + (nfull << 6) < hi) ? 1u : 0u);
+    while (left) {
+        const uint32_t gcount = left < (uint32_t)kUnroll ? left : (uint32_t)kUnroll;
+        uint32_t w[kUnroll], kk[kUnroll];
+        unsigned long long am[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            w[j] = 0;
+            kk[j] = 0;
+            am[j] = 0;
+            if ((uint32_t)j < gcount) {
+                if (c < nfull) {
+                    fetch(w[j], kk[j]);
+                    am[j] = ~0ull;
+                    ++c;
+                } else {
+                    const bool act = lo + (nfull << 6) + (uint32_t)lane < hi;
+                    if (act) {
+                        if (cur >= end) advance();
+                        w[j] = load();
+                    }
+                    kk[j] = k;
+                    am[j] = __ballot(act);
+                }
+            }
         }
-        const uint32_t b = hash_of<HK>(w, pr.B);
-        const Bucket<S> v = read_bucket<S>(pr.slots, b);
-        resolve(v, w, b, k, __ballot(act));
+        uint32_t b[kUnroll];
+        Bucket<S> v[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            if ((uint32_t)j < gcount) {
+                b[j] = hash_of<HK>(w[j], pr.B);
+                v[j] = read_bucket<S>(pr.slots, b[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j)
+            if ((uint32_t)j < gcount) resolve(v[j], w[j], b[j], kk[j], am[j]);
+        left -= gcount;
     }
     while (pm) step_parked();
     if constexpr (PV) {
@@ -430,15 +438,20 @@ __device__ __forceinline__ unsigned long long probe_range(const Probe& pr, uint3
 }
 
 // Process vertex u with a group of `gsz` lanes (one wavefront, or the workgroup when WG).
-template <int S, bool PV, int HK, bool WG, bool DEFER>
-__device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t* tbl, uint64_t avail, int gl,
-                                        int gsz, int gwave, int gnw, int lane, uint32_t* s_wsum,
-                                        unsigned long long& acc) {
-    u = __builtin_amdgcn_readfirstlane(u);
+struct NoMid {
+    __device__ void operator()() const {}
+};
+
+// u's list is col[beg, beg + d) (uniform values).  With `pre` (one wavefront, d <= 64; uniform) the
+// lane's list element and that element's list (start, length) were loaded by the caller (xw, xo, xl).
+// `mid` runs after the table is built and before the probe (the caller issues its next loads there).
+template <int S, bool PV, int HK, bool WG, bool DEFER, typename Mid = NoMid>
+__device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t beg, uint32_t d, uint32_t* tbl,
+                                        uint64_t avail, int gl, int gsz, int gwave, int gnw, int lane,
+                                        uint32_t* s_wsum, unsigned long long& acc, bool pre = false,
+                                        uint32_t xw = 0, uint32_t xo = 0, uint32_t xl = 0, Mid mid = Mid{}) {
     gwave = __builtin_amdgcn_readfirstlane(gwave);
-    const int64_t beg = a.off[u];
-    const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(a.off[u + 1] - beg));
-    const Geometry g = geometry_fit(d, S, a.load_pct, PV, avail);
+    const Geometry g = geometry_fit(d, S, a.lrecip, PV, (uint32_t)avail);
     uint32_t* slots = tbl;
     uint32_t* len = tbl + g.o_len;
     u32x2* P = reinterpret_cast<u32x2*>(tbl + g.o_P);
@@ -454,8 +467,7 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
     group_sync<WG>();
 
     // Build the table of N+(u); record each out-neighbour's 2-hop list (length, start).
-    for (uint32_t p = gl; p < d; p += gsz) {
-        const uint32_t w = a.col[beg + p];
+    auto insert = [&](uint32_t w) {
         uint32_t b = hash_of<HK>(w, g.B), pos;
         for (;;) {
             pos = atomicAdd(&len[b], 1u);
@@ -463,8 +475,19 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
             b = (b + 1) & g.mask;
         }
         slots[b * S + pos] = w;
-        const int64_t o0 = a.off[w], o1 = a.off[w + 1];
-        P[p] = u32x2{(uint32_t)(o1 - o0), (uint32_t)o0};
+    };
+    if (!WG && pre) {
+        if ((uint32_t)gl < d) {
+            insert(xw);
+            P[gl] = u32x2{xl, xo};
+        }
+    } else {
+        for (uint32_t p = gl; p < d; p += gsz) {
+            const uint32_t w = a.col[beg + p];
+            insert(w);
+            const int64_t o0 = a.off[w], o1 = a.off[w + 1];
+            P[p] = u32x2{(uint32_t)(o1 - o0), (uint32_t)o0};
+        }
     }
     group_sync<WG>();
 
@@ -474,7 +497,7 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
         const uint32_t p = t0 + gl;
         u32x2 r = u32x2{0u, 0u};
         if (p < d) r = P[p];
-        uint32_t incl = wave_incl_scan(r.x, lane), tot;
+        uint32_t incl = wave_incl_scan(r.x), tot;
         if constexpr (WG) {
             if (lane == 63) s_wsum[gwave] = incl;
             __syncthreads();
@@ -488,7 +511,7 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
             __syncthreads();
             incl += pre;
         } else {
-            tot = __shfl(incl, 63, 64);
+            tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         }
         if (p < d) {
             const uint32_t e = carry + incl;
@@ -497,6 +520,8 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
         carry += tot;
     }
     group_sync<WG>();
+
+    mid();
 
     // Probe: the group's wavefronts split [0, W) into contiguous ranges.
     const uint32_t W = __builtin_amdgcn_readfirstlane(carry);
@@ -523,6 +548,16 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, uint32_t
         }
     }
     group_sync<WG>();  // the table memory is reused by the next vertex
+}
+
+// Workgroup-owned vertex: its list from the offsets, then process().
+template <int S, bool PV, int HK, bool DEFER>
+__device__ __forceinline__ void process_wg(const CountArgs& a, uint32_t u, uint32_t* tbl, uint64_t avail, int tid,
+                                           int wave, int nw, int lane, uint32_t* s_wsum, unsigned long long& acc) {
+    u = __builtin_amdgcn_readfirstlane(u);
+    const int64_t beg = a.off[u];
+    const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(a.off[u + 1] - beg));
+    process<S, PV, HK, true, DEFER>(a, u, beg, d, tbl, avail, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
 }
 
 // Sum of the workgroup's per-wavefront totals, one atomic per workgroup.
@@ -555,23 +590,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     if (blockIdx.x < a.hub_wgs && n_hub) {
         uint32_t* gt = a.hub_scratch + (size_t)blockIdx.x * a.hub_words;
         for (;;) {
-            if (tid == 0) s_item = atomicAdd(&a.heads[0], 1u);
+            if (tid == 0) s_item = atomicAdd(&a.heads[0 * kHeadStride], 1u);
             __syncthreads();
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_hub) break;
-            process<S, PV, HK, true, false>(a, a.items[j], gt, a.hub_words, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
+            process_wg<S, PV, HK, false>(a, a.items[j], gt, a.hub_words, tid, wave, nw, lane, s_wsum, acc);
         }
     }
     if (n_big) {
         for (;;) {
-            if (tid == 0) s_item = atomicAdd(&a.heads[1], 1u);
+            if (tid == 0) s_item = atomicAdd(&a.heads[1 * kHeadStride], 1u);
             __syncthreads();
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_big) break;
-            process<S, PV, HK, true, true>(a, a.items[n_hub + j], lds, a.table_words, tid, blockDim.x, wave, nw, lane,
-                                           s_wsum, acc);
+            process_wg<S, PV, HK, true>(a, a.items[n_hub + j], lds, a.table_words, tid, wave, nw, lane, s_wsum, acc);
         }
     }
     add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);
@@ -591,27 +625,93 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     // Workgroup bin: the table fills the workgroup's LDS.
     if (n_wg) {
         for (;;) {
-            if (tid == 0) s_item = atomicAdd(&a.heads[2], 1u);
+            if (tid == 0) s_item = atomicAdd(&a.heads[2 * kHeadStride], 1u);
             __syncthreads();
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_wg) break;
-            process<S, PV, HK, true, true>(a, a.items[n_before + j], lds, a.table_words, tid, blockDim.x, wave, nw, lane,
-                                           s_wsum, acc);
+            process_wg<S, PV, HK, true>(a, a.items[n_before + j], lds, a.table_words, tid, wave, nw, lane, s_wsum,
+                                        acc);
         }
     }
-    // Wavefront bin: each wavefront owns a slice of the LDS.
+    // Wavefront bin: each wavefront owns a slice of the LDS and takes `chunk` vertices at a time.
+    // Chunk c belongs to sub-queue c % kWaveQueues (interleaved, so every sub-queue keeps the
+    // largest-work-first order); each sub-queue counter has a cache line of its own, which spreads
+    // the fetch atomics of a launch with millions of light vertices over kWaveQueues addresses.  A
+    // wavefront starts on sub-queue blockIdx % kWaveQueues (one per XCD with round-robin dispatch),
+    // moves on when its sub-queue is drained, and requests its next chunk before working on the
+    // current one.
     {
         uint32_t* slice = lds + (size_t)wave * a.slice_words;
         const uint32_t base = n_before + n_wg;
-        for (;;) {
-            uint32_t j0 = 0;
-            if (lane == 0) j0 = atomicAdd(&a.heads[3], a.chunk);
-            j0 = __builtin_amdgcn_readfirstlane(j0);
-            if (j0 >= n_wave) break;
+        const uint32_t nchunks = (n_wave + a.chunk - 1) / a.chunk;
+        uint32_t q = blockIdx.x % kWaveQueues, drained = 0;
+        auto request = [&]() -> uint32_t {
+            uint32_t c = 0;
+            if (lane == 0) c = atomicAdd(&a.heads[(3 + q) * kHeadStride], 1u);
+            return c;
+        };
+        // Chunk index from a sub-queue ticket, moving on through drained sub-queues (nchunks: all done).
+        auto settle = [&](uint32_t ticket) -> uint32_t {
+            for (;;) {
+                const uint32_t g = __builtin_amdgcn_readfirstlane(ticket) * kWaveQueues + q;
+                if (g < nchunks) return g;
+                if (++drained >= kWaveQueues) return nchunks;
+                q = (q + 1) % kWaveQueues;
+                ticket = request();
+            }
+        };
+        uint32_t cur = settle(request());
+        while (cur < nchunks) {
+            const uint32_t ticket = request();  // next chunk, settled after this one
+            const uint32_t j0 = cur * a.chunk;
             const uint32_t j1 = (j0 + a.chunk < n_wave) ? j0 + a.chunk : n_wave;
-            for (uint32_t j = j0; j < j1; ++j)
-                process<S, PV, HK, false, true>(a, a.items[base + j], slice, a.slice_words, lane, 64, 0, 1, lane, nullptr, acc);
+            // The vertices of a fetch and their list bounds are loaded by the wavefront at once
+            // (lane i holds the i-th), so each vertex starts without two dependent loads.
+            for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
+                const uint32_t cnt = (j1 - b0 < 64u) ? j1 - b0 : 64u;
+                uint32_t vu = 0, vb = 0, vd = 0;  // offsets stay below 2^31 (m < 2^31)
+                if ((uint32_t)lane < cnt) {
+                    vu = a.items[base + b0 + lane];
+                    vb = (uint32_t)a.off[vu];
+                    vd = (uint32_t)a.off[vu + 1] - vb;
+                }
+                // Two-stage prefetch for lists of at most 64: the next vertex's list is loaded while
+                // this one's table is built, and its elements' list bounds while this one is probed.
+                uint32_t xw = 0, xo = 0, xl = 0;
+                {
+                    const int64_t beg0 = (int64_t)__builtin_amdgcn_readlane(vb, 0);
+                    const uint32_t d0 = __builtin_amdgcn_readlane(vd, 0);
+                    if (d0 <= 64u && (uint32_t)lane < d0) {
+                        xw = a.col[beg0 + lane];
+                        xo = (uint32_t)a.off[xw];
+                        xl = (uint32_t)a.off[xw + 1] - xo;
+                    }
+                }
+                for (uint32_t i = 0; i < cnt; ++i) {
+                    const uint32_t u = __builtin_amdgcn_readlane(vu, i);
+                    const int64_t beg = (int64_t)__builtin_amdgcn_readlane(vb, i);
+                    const uint32_t d = __builtin_amdgcn_readlane(vd, i);
+                    const uint32_t inext = i + 1 < cnt ? i + 1 : i;
+                    const int64_t beg_n = (int64_t)__builtin_amdgcn_readlane(vb, inext);
+                    const uint32_t d_n = i + 1 < cnt ? __builtin_amdgcn_readlane(vd, inext) : 0u;
+                    const bool pre_n = d_n <= 64u && (uint32_t)lane < d_n;
+                    uint32_t nw = 0, no = 0, nl = 0;
+                    if (pre_n) nw = a.col[beg_n + lane];
+                    auto mid = [&]() {
+                        if (pre_n) {
+                            no = (uint32_t)a.off[nw];
+                            nl = (uint32_t)a.off[nw + 1] - no;
+                        }
+                    };
+                    process<S, PV, HK, false, true>(a, u, beg, d, slice, a.slice_words, lane, 64, 0, 1, lane, nullptr,
+                                                    acc, d <= 64u, xw, xo, xl, mid);
+                    xw = nw;
+                    xo = no;
+                    xl = nl;
+                }
+            }
+            cur = settle(ticket);
         }
     }
     add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);

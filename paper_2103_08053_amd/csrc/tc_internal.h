@@ -12,6 +12,11 @@ namespace tc {
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash slot; never a valid id (ids < n <= 2^32 - 1)
 constexpr uint32_t kMaxWaves = 16;
 constexpr uint32_t kHubWgs = 128;        // workgroups that take global-memory-table vertices
+// Queue heads of the count launches: bins 0-2 and kWaveQueues sub-queues of the wavefront bin, each
+// counter in a 128-byte line of its own (kHeadStride words apart).
+constexpr uint32_t kWaveQueues = 8;
+constexpr uint32_t kHeadStride = 32;
+constexpr uint32_t kHeadWords = (3 + kWaveQueues) * kHeadStride;
 
 // Device-resident summary of a built graph (first 256 bytes of its storage).
 struct GraphMeta {
@@ -37,11 +42,13 @@ struct Geometry {
     uint32_t B, mask, o_len, o_P, o_tslot, o_tally, words;
 };
 
-__host__ __device__ inline uint32_t next_pow2(uint32_t x) {
-    uint32_t p = 1;
-    while (p < x) p <<= 1;
-    return p;
-}
+// Smallest power of two >= x, and largest power of two <= x (0 for x = 0).
+__host__ __device__ inline uint32_t pow2_ceil(uint32_t x) { return x <= 1 ? 1u : 1u << (32 - __builtin_clz(x - 1)); }
+__host__ __device__ inline uint32_t pow2_floor(uint32_t x) { return x ? 1u << (31 - __builtin_clz(x)) : 0u; }
+
+// Slots per element a load factor asks for, in 16-bit fixed point (rounded up): ceil(100 * 2^16 / load).
+// Host and device size tables from this same value, so a vertex binned by the host fits on the device.
+__host__ __device__ inline uint32_t load_recip(uint32_t load_pct) { return (100u * 65536u + load_pct - 1) / load_pct; }
 
 // Layout for d elements in B buckets.
 __host__ __device__ inline Geometry geometry_b(uint32_t d, uint32_t S, uint32_t B, bool pv) {
@@ -56,36 +63,40 @@ __host__ __device__ inline Geometry geometry_b(uint32_t d, uint32_t S, uint32_t 
     return g;
 }
 
-// The smallest table the load factor allows (used to decide which bin a vertex fits).
-__host__ __device__ inline Geometry geometry(uint32_t d, uint32_t S, uint32_t load_pct, bool pv) {
-    uint32_t need = (d + S) / S;                                // B*S > d
-    uint32_t c = (uint32_t)(((uint64_t)d * 100 + (uint64_t)S * load_pct - 1) / ((uint64_t)S * load_pct));
+// The smallest table the load factor allows (used to decide which bin a vertex fits):
+// B*S > d and B*S >= d * 100 / load (lrecip = load_recip(load)).
+__host__ __device__ inline Geometry geometry(uint32_t d, uint32_t S, uint32_t lrecip, bool pv) {
+    uint32_t need = d / S + 1;
+    const uint64_t slots = ((uint64_t)d * lrecip + 65535u) >> 16;
+    const uint32_t c = (uint32_t)((slots + S - 1) / S);
     if (c > need) need = c;
-    return geometry_b(d, S, next_pow2(need), pv);
+    return geometry_b(d, S, pow2_ceil(need), pv);
 }
 
-// The table actually used: the minimal one grown (doubling B) while it fits
-// `avail` words and holds at most max(64, 8 d) slots, so a vertex whose
-// region has room gets a lightly loaded table (fewer full buckets to walk).
-__host__ __device__ inline Geometry geometry_fit(uint32_t d, uint32_t S, uint32_t load_pct, bool pv,
-                                                 uint64_t avail) {
-    Geometry g = geometry(d, S, load_pct, pv);
-    const uint64_t cap = 8ull * d > 64ull ? 8ull * d : 64ull;
-    for (;;) {
-        if ((uint64_t)g.B * 2 * S > cap) break;
-        const Geometry h = geometry_b(d, S, g.B * 2, pv);
-        if (h.words > avail) break;
-        g = h;
-    }
-    return g;
+// The table actually used: the largest power-of-two B at least the minimal one that fits `avail`
+// words and holds at most max(64, 8 d) slots, so a vertex whose region has room gets a lightly loaded
+// table (fewer full buckets to walk).  words(B) <= B (S (1 + pv) + 1) + (2 + pv) d + 8 bounds the
+// layout, which gives B in closed form.
+__host__ __device__ inline Geometry geometry_fit(uint32_t d, uint32_t S, uint32_t lrecip, bool pv, uint32_t avail) {
+    const Geometry g = geometry(d, S, lrecip, pv);
+    const uint32_t cap_slots = d > 8u ? 8u * d : 64u;
+    uint32_t B = pow2_floor(cap_slots / S);
+    const uint32_t fixed = (pv ? 3u : 2u) * d + 8u;
+    const uint32_t per_b = S * (pv ? 2u : 1u) + 1u;
+    const uint32_t bw = avail > fixed ? pow2_floor((avail - fixed) / per_b) : 0u;
+    if (bw < B) B = bw;
+    if (B <= g.B) return g;
+    const Geometry h = geometry_b(d, S, B, pv);
+    return h.words <= avail ? h : g;
 }
 
 // Largest d whose table fits in `words` 32-bit words (0 if none).
 inline uint32_t capacity(uint32_t words, uint32_t S, uint32_t load_pct, bool pv) {
+    const uint32_t lr = load_recip(load_pct);
     uint32_t lo = 0, hi = words;  // words(d) >= 2d, so d <= words / 2
     while (lo < hi) {
         uint32_t mid = lo + (hi - lo + 1) / 2;
-        if (geometry(mid, S, load_pct, pv).words <= words) lo = mid; else hi = mid - 1;
+        if (geometry(mid, S, lr, pv).words <= words) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -143,7 +154,7 @@ struct CountArgs {
     const int64_t* off;
     const uint32_t* col;
     const uint32_t* items;
-    uint32_t* heads;                 // [4] queue heads, one per bin (zeroed before the launches)
+    uint32_t* heads;                 // [kHeadWords] queue heads (zeroed before the launches)
     unsigned long long* total;       // [1] (zeroed before launch); single-graph mode
     const uint32_t* gid;             // [n] graph of each rank (batch mode), or null
     unsigned long long* totals;      // [k] per-graph totals (batch mode, zeroed before launch)
@@ -153,7 +164,7 @@ struct CountArgs {
     uint32_t hub_wgs;                // workgroups of the large-table launch that take global-table vertices
     uint32_t slice_words;            // per-wavefront LDS slice
     uint32_t table_words;            // LDS words of the workgroup table region (of this launch)
-    uint32_t load_pct;
+    uint32_t lrecip;                 // load_recip(load factor)
     uint32_t chunk;
     uint32_t wide;                   // col spans 4 GiB or more: 64-bit addressing in the probe
 };

@@ -349,7 +349,7 @@ tc_status tc_default_params(tc_params* p) {
     p->slots_per_bucket = 4;
     p->load_factor_pct = 50;
     p->hash_kind = 0;
-    p->light_chunk = 16;
+    p->light_chunk = 8;
     p->grid_wgs = 0;
     p->flags = 0;
     return TC_OK;

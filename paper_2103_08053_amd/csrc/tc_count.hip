@@ -449,7 +449,8 @@ template <int S, bool PV, int HK, bool WG, bool DEFER, typename Mid = NoMid>
 __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t beg, uint32_t d, uint32_t* tbl,
                                         uint64_t avail, int gl, int gsz, int gwave, int gnw, int lane,
                                         uint32_t* s_wsum, unsigned long long& acc, bool pre = false,
-                                        uint32_t xw = 0, uint32_t xo = 0, uint32_t xl = 0, Mid mid = Mid{}) {
+                                        uint32_t xw = 0, uint32_t xo = 0, uint32_t xl = 0, Mid mid = Mid{},
+                                        uint32_t part = 0, uint32_t parts = 1) {
     gwave = __builtin_amdgcn_readfirstlane(gwave);
     const Geometry g = geometry_fit(d, S, a.lrecip, PV, (uint32_t)avail);
     uint32_t* slots = tbl;
@@ -525,8 +526,11 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
 
     // Probe: the group's wavefronts split [0, W) into contiguous ranges.
     const uint32_t W = __builtin_amdgcn_readfirstlane(carry);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * gwave) / gnw));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * (gwave + 1)) / gnw));
+    // With parts > 1 several groups take the same vertex, each its share of [0, W) (tallies and hits
+    // are sums, so partial flushes add up).
+    const uint32_t r = part * (uint32_t)gnw + (uint32_t)gwave, rn = parts * (uint32_t)gnw;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * r) / rn));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * (r + 1)) / rn));
     const Probe pr{a.col, slots, P, tslot, tally, g.B};
     const unsigned long long hits = probe_range<S, PV, HK, DEFER>(pr, d, lo, hi, lane, a.wide);
     if (a.gid) {
@@ -553,11 +557,19 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
 // Workgroup-owned vertex: its list from the offsets, then process().
 template <int S, bool PV, int HK, bool DEFER>
 __device__ __forceinline__ void process_wg(const CountArgs& a, uint32_t u, uint32_t* tbl, uint64_t avail, int tid,
-                                           int wave, int nw, int lane, uint32_t* s_wsum, unsigned long long& acc) {
+                                           int wave, int nw, int lane, uint32_t* s_wsum, unsigned long long& acc,
+                                           uint32_t part = 0, uint32_t parts = 1) {
     u = __builtin_amdgcn_readfirstlane(u);
     const int64_t beg = a.off[u];
     const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(a.off[u + 1] - beg));
-    process<S, PV, HK, true, DEFER>(a, u, beg, d, tbl, avail, tid, blockDim.x, wave, nw, lane, s_wsum, acc);
+    process<S, PV, HK, true, DEFER>(a, u, beg, d, tbl, avail, tid, blockDim.x, wave, nw, lane, s_wsum, acc, false,
+                                    0u, 0u, 0u, NoMid{}, part, parts);
+}
+
+// Tickets of a large-vertex bin of n vertices for `wgs` workgroups: when the bin has fewer vertices
+// than workgroups, each vertex is split into `parts` tickets (consecutive), one per share of its work.
+__device__ __forceinline__ uint32_t parts_for(uint32_t n, uint32_t wgs) {
+    return (n && wgs > n) ? wgs / n : 1u;
 }
 
 // Sum of the workgroup's per-wavefront totals, one atomic per workgroup.
@@ -589,23 +601,27 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
 
     if (blockIdx.x < a.hub_wgs && n_hub) {
         uint32_t* gt = a.hub_scratch + (size_t)blockIdx.x * a.hub_words;
+        const uint32_t parts = parts_for(n_hub, a.hub_wgs);
         for (;;) {
             if (tid == 0) s_item = atomicAdd(&a.heads[0 * kHeadStride], 1u);
             __syncthreads();
-            const uint32_t j = s_item;
+            const uint32_t t = s_item;
             __syncthreads();
-            if (j >= n_hub) break;
-            process_wg<S, PV, HK, false>(a, a.items[j], gt, a.hub_words, tid, wave, nw, lane, s_wsum, acc);
+            if (t >= n_hub * parts) break;
+            process_wg<S, PV, HK, false>(a, a.items[t / parts], gt, a.hub_words, tid, wave, nw, lane, s_wsum, acc,
+                                         t % parts, parts);
         }
     }
     if (n_big) {
+        const uint32_t parts = parts_for(n_big, gridDim.x);
         for (;;) {
             if (tid == 0) s_item = atomicAdd(&a.heads[1 * kHeadStride], 1u);
             __syncthreads();
-            const uint32_t j = s_item;
+            const uint32_t t = s_item;
             __syncthreads();
-            if (j >= n_big) break;
-            process_wg<S, PV, HK, true>(a, a.items[n_hub + j], lds, a.table_words, tid, wave, nw, lane, s_wsum, acc);
+            if (t >= n_big * parts) break;
+            process_wg<S, PV, HK, true>(a, a.items[n_hub + t / parts], lds, a.table_words, tid, wave, nw, lane, s_wsum,
+                                        acc, t % parts, parts);
         }
     }
     add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);

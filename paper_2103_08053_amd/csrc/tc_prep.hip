@@ -18,6 +18,7 @@
 //     Equation 2); vertices with d+ < 2 or W = 0 are skipped, the rest go to
 //     a global-memory-table bin, a workgroup bin or a wavefront bin by d+,
 //     and each bin is ordered by decreasing W (largest work first).
+#include <algorithm>
 #include <cstring>
 
 #include <rocprim/rocprim.hpp>
@@ -466,7 +467,8 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
         TC_TRY(rocprim::inclusive_scan(t.sort_tmp, tmp, heads, wscan, (size_t)m_in,
                                        rocprim::plus<unsigned long long>(), stream));
     }
-    hipLaunchKernelGGL(k_schedule, dim3(grid_for(n)), dim3(kThreads), 0, stream, g.off, wscan, n, caps, g.meta,
+    // at most 1024 blocks: each block ends with a few global atomics on the same summary words
+    hipLaunchKernelGGL(k_schedule, dim3(std::min(grid_for(n), 1024u)), dim3(kThreads), 0, stream, g.off, wscan, n, caps, g.meta,
                        t.skey_a);
     TC_TRY(hipGetLastError());
     tmp = t.sort_tmp_bytes;

@@ -106,9 +106,14 @@ class Server:
         nxt = 0
         done = 0
         batches = 0
+        busy = 0.0  # host-observed time with at least one batch on the device
         t0 = time.perf_counter()
+        last = 0.0
         while done < len(requests):
             now = time.perf_counter() - t0
+            if inflight:
+                busy += now - last
+            last = now
             while nxt < len(order) and arrivals[order[nxt]] <= now:
                 r = requests[order[nxt]]
                 r.arrival = float(arrivals[order[nxt]])
@@ -153,7 +158,9 @@ class Server:
             else:
                 time.sleep(idle_sleep)
         wall = time.perf_counter() - t0
-        return summarize(requests, wall, batches)
+        out = summarize(requests, wall, batches)
+        out["device_busy_frac"] = busy / wall
+        return out
 
 
 def serve_fifo(ctx: Context, requests: list[Request], arrivals: np.ndarray):

@@ -67,8 +67,8 @@ typedef struct tc_params {
 #define TC_F_NO_LPT     0x1u    /* keep rank order instead of largest-work-first within each bin */
 #define TC_F_FORCE_WG   0x2u    /* every vertex goes to the workgroup bin (tests) */
 #define TC_F_FORCE_HUB  0x4u    /* every vertex goes to the global-memory table bin (tests) */
-#define TC_F_SCATTER_CSR 0x8u   /* build the CSR by an atomic counting sort (lists unordered) instead of
-                                   the default radix sort of the oriented edges (lists sorted by rank) */
+#define TC_F_SCATTER_CSR 0x8u   /* build the CSR by an atomic counting sort (list order unspecified) instead
+                                   of the default stable radix sort of the oriented edges by row */
 #define TC_F_WIDE_ADDR  0x10u   /* 64-bit list addressing even below 2^30 edges (tests) */
 #define TC_F_FORCE_BIG  0x20u   /* every vertex goes to the large-LDS-table bin (tests) */
 

@@ -430,14 +430,16 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
 
     // 4-5: orientation and CSR in rank space.
     if (!caps.scatter_csr) {
-        // Sort the oriented keys: rows come out contiguous and each list sorted by rank.
+        // Sort the oriented keys by row only (the high nb bits; radix sort is stable, so each list keeps
+        // the canonical-key order; lists need no order for hashing): rows come out contiguous.  The
+        // sentinel's row bits exceed every valid row, so unused entries sort last.
         unsigned long long* okeys = t.keys_a;
         unsigned long long* osorted = reinterpret_cast<unsigned long long*>(t.aux);
         hipLaunchKernelGGL(k_orient_keys, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_b, nb, m_in, g.rank,
                            sentinel, okeys);
         TC_TRY(hipGetLastError());
         tmp = t.sort_tmp_bytes;
-        TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, okeys, osorted, (size_t)m_in, 0, 2 * nb, stream));
+        TC_TRY(rocprim::radix_sort_keys(t.sort_tmp, tmp, okeys, osorted, (size_t)m_in, nb, 2 * nb, stream));
         hipLaunchKernelGGL(k_csr_runs, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, osorted, nb, m_in, g.meta,
                            t.dplus, g.col);
         TC_TRY(hipGetLastError());

@@ -195,6 +195,27 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_shards(args, ctx, graph, info, total, per_vertex):
+    """Workload partitioning on one GPU: the count split into `args.shards` partitions (rank mod g),
+    each timed alone; their sum must equal the whole count."""
+    import torch
+    pv = torch.empty(max(graph.n, 1), dtype=torch.int64, device=graph.storage.device) if per_vertex else None
+    ms, tots = [], []
+    for s in range(args.shards):
+        graph.count_async(pv, shard=(s, args.shards))  # warm
+        runs = []
+        for _ in range(3):
+            graph.count_async(pv, shard=(s, args.shards))
+            runs.append(ctx.last_times_ms()[1])
+        ms.append(sorted(runs)[1])
+        tots.append(int(graph.totals_dev[0].item()))
+    assert sum(tots) == total, (sum(tots), total)
+    mean = sum(ms) / len(ms)
+    return {"shards": args.shards, "shard_count_ms": ms, "shard_triangles": tots,
+            "max_over_mean": max(ms) / mean, "sum_of_shards_ms": sum(ms),
+            "triangles_max_over_mean": max(tots) / (sum(tots) / len(tots))}
+
+
 def run_serve(args):
     """Poisson request stream over a pinned-host pool; continuous batching vs FIFO plain path."""
     import numpy as np
@@ -258,6 +279,8 @@ def main():
     ap.add_argument("--serve-max-scale", type=int, default=20)
     ap.add_argument("--hbm-budget-gb", type=int, default=96)
     ap.add_argument("--max-batch", type=int, default=256)
+    ap.add_argument("--shards", type=int, default=0,
+                    help="with a single-graph workload: also time its count as this many workload partitions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design "
@@ -322,9 +345,10 @@ def main():
         ms = ctx.last_times_ms()[1]
         if i >= args.warmup:
             kms.append(ms)
-    ctx.timing(False)
     tot2 = int(graph.total_dev.item())
     assert tot2 == total, (tot2, total)
+    shards = run_shards(args, ctx, graph, info, total, per_vertex) if args.shards > 1 else None
+    ctx.timing(False)
     kernel_ms = float(np.mean(kms))
     log(f"[bench] count kernel {kernel_ms:.3f} ms (min {min(kms):.3f}), build {np.mean(build_ms):.3f} ms, "
         f"info {info}")
@@ -349,9 +373,13 @@ def main():
         "build_ms": float(np.mean(build_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_vertex, args.workload),
-                     "kernel": "tc_count_kernel", "algorithmic_bytes": b_alg,
+                     "kernel": "tc_count_kernel (after tc_hub_kernel, both inside the events)",
+                     "algorithmic_bytes": b_alg,
                      "kernel_source_sha1": kernel_source_sha1()},
     }
+    if shards:
+        out["workload_partitions"] = shards
+        log(f"[bench] shards: {shards}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, info, args.cpu_stride)

@@ -182,6 +182,21 @@ tc_status tc_batch_build(tc_context* ctx, uint32_t k, uint32_t n_total, uint64_t
 tc_status tc_graph_count_each(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex,
                               void* d_scratch, uint64_t scratch_bytes, void* stream);
 
+/* Workload partitioning (paper Section 5.1): count only the triangles whose
+ * table owner u (the endpoint earliest in (degree, id) order, i.e. lowest
+ * rank) has rank(u) mod shards == shard.  Ranks follow degree, so every
+ * shard gets a similar mix of heavy and light vertices.  d_totals (device
+ * uint64[k], one per graph) and d_per_vertex (NULL or device uint64[n]) are
+ * overwritten with that shard's share; summing the shards 0..shards-1 gives
+ * exactly what tc_graph_count_each gives.  Each shard runs the same launches
+ * over the whole vertex list, skipping vertices of other shards, so shards
+ * can go to different devices holding the same graph.  TC_E_INVALID when
+ * shards == 0 or shard >= shards; scratch as for tc_graph_count_each.
+ * Asynchronous on `stream`. */
+tc_status tc_graph_count_shard(tc_context* ctx, const tc_graph* g, uint32_t shard, uint32_t shards,
+                               uint64_t* d_totals, uint64_t* d_per_vertex, void* d_scratch, uint64_t scratch_bytes,
+                               void* stream);
+
 /* As tc_graph_count_each, but the device work (the clears, the count
  * kernel and the per-vertex gather) is captured once into a HIP graph on a
  * stream owned by ctx and replayed on `stream` by later calls with the same

@@ -258,7 +258,7 @@ bool needs_hub_launch(const tc_graph* g) {
 // The count: clears, the persistent kernel and (per-vertex mode) the gather.
 // d_totals has g->k entries.  With `record` false no timing events are recorded (stream capture).
 tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex, void* scratch,
-                     const Layout& L, hipStream_t s, bool record = true) {
+                     const Layout& L, hipStream_t s, bool record = true, uint32_t shard = 0, uint32_t shards = 1) {
     const tc_params& p = g->p;
     const bool pv = d_per_vertex != nullptr;
     char* b = static_cast<char*>(scratch);
@@ -284,6 +284,8 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.lrecip = tc::load_recip(p.load_factor_pct);
     a.chunk = p.light_chunk;
     a.wide = (g->m_in >= (1ull << 30)) || (p.flags & TC_F_WIDE_ADDR) ? 1u : 0u;
+    a.shard = shard;
+    a.shards = shards;
     const bool hub = needs_hub_launch(g);
     int per_cu = 0, per_cu_hub = 0;
     if (tc_status st = occupancy(ctx, p, pv, false, &per_cu)) return st;
@@ -591,6 +593,19 @@ tc_status tc_batch_build(tc_context* ctx, uint32_t k, uint32_t n_total, uint64_t
     if (s != TC_OK) { delete g; return s; }
     *out = g;
     return TC_OK;
+}
+
+tc_status tc_graph_count_shard(tc_context* ctx, const tc_graph* g, uint32_t shard, uint32_t shards,
+                               uint64_t* d_totals, uint64_t* d_per_vertex, void* d_scratch, uint64_t scratch_bytes,
+                               void* stream) {
+    if (!ctx || !g || !d_totals) return TC_E_INVALID;
+    if (shards == 0 || shard >= shards) return fail(ctx, TC_E_INVALID, "shard %u of %u", shard, shards);
+    ctx->err.clear();
+    const Layout L = layout(ctx, g->p, g->n, g->m_in, g->batch);
+    if (!d_scratch || scratch_bytes < L.scratch) return fail(ctx, TC_E_NOMEM, "scratch too small");
+    if (tc_status s = use_device(ctx)) return s;
+    return count_into(ctx, g, d_totals, d_per_vertex, d_scratch, L, static_cast<hipStream_t>(stream), true, shard,
+                      shards);
 }
 
 tc_status tc_graph_count_each(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex,

@@ -555,11 +555,17 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
 }
 
 // Workgroup-owned vertex: its list from the offsets, then process().
+// Whether this launch counts the triangles owned by u (workload partitioning: u % shards == shard).
+__device__ __forceinline__ bool in_shard(const CountArgs& a, uint32_t u) {
+    return a.shards <= 1 || u % a.shards == a.shard;
+}
+
 template <int S, bool PV, int HK, bool DEFER>
 __device__ __forceinline__ void process_wg(const CountArgs& a, uint32_t u, uint32_t* tbl, uint64_t avail, int tid,
                                            int wave, int nw, int lane, uint32_t* s_wsum, unsigned long long& acc,
                                            uint32_t part = 0, uint32_t parts = 1) {
     u = __builtin_amdgcn_readfirstlane(u);
+    if (!in_shard(a, u)) return;
     const int64_t beg = a.off[u];
     const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(a.off[u + 1] - beg));
     process<S, PV, HK, true, DEFER>(a, u, beg, d, tbl, avail, tid, blockDim.x, wave, nw, lane, s_wsum, acc, false,
@@ -720,8 +726,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                             nl = (uint32_t)a.off[nw + 1] - no;
                         }
                     };
-                    process<S, PV, HK, false, true>(a, u, beg, d, slice, a.slice_words, lane, 64, 0, 1, lane, nullptr,
-                                                    acc, d <= 64u, xw, xo, xl, mid);
+                    if (in_shard(a, u))
+                        process<S, PV, HK, false, true>(a, u, beg, d, slice, a.slice_words, lane, 64, 0, 1, lane,
+                                                        nullptr, acc, d <= 64u, xw, xo, xl, mid);
+                    else
+                        mid();
                     xw = nw;
                     xo = no;
                     xl = nl;

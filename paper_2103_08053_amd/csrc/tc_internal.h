@@ -166,6 +166,7 @@ struct CountArgs {
     uint32_t table_words;            // LDS words of the workgroup table region (of this launch)
     uint32_t lrecip;                 // load_recip(load factor)
     uint32_t chunk;
+    uint32_t shard, shards;          // count only table owners u (rank) with u % shards == shard
     uint32_t wide;                   // col spans 4 GiB or more: 64-bit addressing in the probe
 };
 

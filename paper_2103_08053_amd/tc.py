@@ -22,7 +22,7 @@ EXPORTS = [
     "tc_last_error", "tc_workspace_bytes", "tc_count", "tc_graph_footprint", "tc_graph_build",
     "tc_count_scratch_bytes", "tc_graph_count", "tc_graph_info_get", "tc_graph_release",
     "tc_timing_enable", "tc_timing_last", "tc_batch_footprint", "tc_batch_build", "tc_graph_count_each",
-    "tc_graph_count_replay", "tc_graph_k",
+    "tc_graph_count_replay", "tc_graph_k", "tc_graph_count_shard",
 ]
 
 
@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH):
         "tc_batch_build": [vp, u32, u32, u64, vp, vp, vp, vp, vp, u64, vp, u64, vp, ctypes.POINTER(vp)],
         "tc_graph_count_each": [vp, vp, vp, vp, vp, u64, vp],
         "tc_graph_count_replay": [vp, vp, vp, vp, vp, u64, vp],
+        "tc_graph_count_shard": [vp, vp, u32, u32, vp, vp, vp, u64, vp],
         "tc_graph_k": [vp, ctypes.POINTER(u32)],
         "tc_timing_last": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
     }
@@ -309,18 +310,27 @@ class Graph:
         _check(self.ctx.lib.tc_graph_info_get(self.h, _stream_ptr(stream), ctypes.byref(gi)), self.ctx.h)
         return GraphInfo(**{k: int(getattr(gi, k)) for k, _ in _GraphInfo._fields_})
 
-    def count_async(self, per_vertex_out=None, stream=None, replay: bool = False):
+    def count_async(self, per_vertex_out=None, stream=None, replay: bool = False, shard=None):
         """Launch the count; totals land in ``self.totals_dev`` (device int64[k]).
-        With ``replay`` the device work is captured once into a HIP graph and replayed."""
-        fn = self.ctx.lib.tc_graph_count_replay if replay else self.ctx.lib.tc_graph_count_each
+        With ``replay`` the device work is captured once into a HIP graph and replayed.
+        ``shard=(r, g)`` counts only workload partition r of g (tc_graph_count_shard)."""
+        lib = self.ctx.lib
+        if shard is not None:
+            if replay:
+                raise ValueError("replay counts the whole graph")
+            r, g = shard
+            _check(lib.tc_graph_count_shard(self.ctx.h, self.h, r, g, _ptr(self.totals_dev), _ptr(per_vertex_out),
+                                            _ptr(self.scratch), self.scratch.numel(), _stream_ptr(stream)), self.ctx.h)
+            return
+        fn = lib.tc_graph_count_replay if replay else lib.tc_graph_count_each
         _check(fn(self.ctx.h, self.h, _ptr(self.totals_dev), _ptr(per_vertex_out), _ptr(self.scratch),
                   self.scratch.numel(), _stream_ptr(stream)), self.ctx.h)
 
-    def count(self, per_vertex: bool = False, stream=None, replay: bool = False):
+    def count(self, per_vertex: bool = False, stream=None, replay: bool = False, shard=None):
         """(total, per-vertex tensor or None) for a single graph; (totals list, ...) for a batch."""
         torch = _torch()
         pv = torch.empty(max(self.n, 1), dtype=torch.int64, device=self.storage.device) if per_vertex else None
-        self.count_async(pv, stream, replay=replay)
+        self.count_async(pv, stream, replay=replay, shard=shard)
         tot = self.totals_dev.cpu().tolist()
         return (tot[0] if self.k == 1 else tot), (pv[: self.n] if per_vertex else None)
 

@@ -251,3 +251,65 @@ def test_rmat_scale26_full_size(ctx, torch):
     """R-MAT scale 26 (about 1.05e9 edges): col past 4 GiB, so the count takes
     the 64-bit addressing variant; skewed hubs."""
     check_full_size(ctx, "rmat26", W.huge_rmat, one_shot=False)
+
+
+# ----------------------------------------------------------------------------- workload partitioning
+
+def owned_counts(g):
+    """Triangles per table owner u (the (degree, id)-lowest vertex of the triangle), from the oracle's
+    oriented lists: sum over v in N+(u) of |N+(u) & N+(v)|; and each vertex's rank in (degree, id) order."""
+    deg, dplus, nbr = oracle.oriented(g.n, g.src, g.dst)
+    off = np.concatenate([[0], np.cumsum(dplus.astype(np.int64))])
+    lists = [set(nbr[off[u]:off[u + 1]].tolist()) for u in range(g.n)]
+    own = np.array([sum(len(lists[u] & lists[v]) for v in lists[u]) for u in range(g.n)], np.int64)
+    order = np.lexsort((np.arange(g.n), deg))  # by degree, then id
+    rank = np.empty(g.n, np.int64)
+    rank[order] = np.arange(g.n)
+    return own, rank
+
+
+@pytest.mark.parametrize("shards", [2, 3, 8])
+def test_shards_sum_to_whole(ctx, torch, shards):
+    """Workload partitions (table owner's rank mod shards) add up to the whole count, total and per
+    vertex, and each shard's total is the number of triangles whose lowest-rank vertex is in it."""
+    g = gg.dirty(gg.rmat(12, 16, seed=5), seed=6)
+    r = oracle.count(g.n, g.src, g.dst, per_vertex=True)
+    own, rank = owned_counts(g)
+    assert own.sum() == r.total
+    graph = ctx.build(g.src, g.dst, g.n)
+    tot, pv = 0, np.zeros(g.n, np.uint64)
+    parts = []
+    for s in range(shards):
+        t, p = graph.count(per_vertex=True, shard=(s, shards))
+        assert t == int(own[rank % shards == s].sum()), s
+        parts.append(t)
+        tot += t
+        pv += p.cpu().numpy().astype(np.uint64)
+    assert tot == r.total
+    assert (pv == r.per_vertex).all()
+    if shards == 8:
+        # rank order spreads the work: no shard holds more than twice its even share
+        assert max(parts) <= 2 * r.total / shards
+
+
+def test_shards_batch_and_forced_paths(torch):
+    from paper_2103_08053_amd import Batch, Context, Params
+    gs = [gg.complete(40), gg.wheel(60), gg.dirty(gg.rmat(11, 16, seed=2), seed=3), gg.friendship(30)]
+    for kw in (dict(), dict(flags=4), dict(flags=32), dict(wg_lds_bytes=4096, wg_waves=4)):
+        c = Context(0, Params(**kw))
+        b = Batch(c, [(g.n, g.src, g.dst) for g in gs])
+        whole = b.count()[0]
+        acc = [0] * len(gs)
+        for s in range(4):
+            part = b.count(shard=(s, 4))[0]
+            acc = [x + y for x, y in zip(acc, part)]
+        assert acc == whole == [oracle.count(g.n, g.src, g.dst).total for g in gs], kw
+
+
+def test_shard_arguments_checked(ctx, torch):
+    from paper_2103_08053_amd import TCError
+    g = gg.complete(10)
+    graph = ctx.build(g.src, g.dst, g.n)
+    for bad in ((0, 0), (3, 3), (5, 2)):
+        with pytest.raises(TCError):
+            graph.count(shard=bad)

@@ -279,6 +279,9 @@ def main():
     ap.add_argument("--serve-max-scale", type=int, default=20)
     ap.add_argument("--hbm-budget-gb", type=int, default=96)
     ap.add_argument("--max-batch", type=int, default=256)
+    ap.add_argument("--flags", type=int, default=0, help="extra TC_F_* flags for the single-graph workloads "
+                    "(e.g. 64: in-degree vertex order, 128: collective-degree order)")
+    ap.add_argument("--collisions", action="store_true", help="also report the tables' collision statistics")
     ap.add_argument("--shards", type=int, default=0,
                     help="with a single-graph workload: also time its count as this many workload partitions")
     args = ap.parse_args()
@@ -294,7 +297,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2103_08053_amd import Context
+    from paper_2103_08053_amd import Context, Params
 
     per_vertex = not args.no_per_vertex
     if args.pmc_calibrate:
@@ -305,7 +308,7 @@ def main():
     dev = torch.device("cuda", 0)
     src = torch.from_numpy(g.src.view(np.int32)).to(dev)
     dst = torch.from_numpy(g.dst.view(np.int32)).to(dev)
-    ctx = Context(0)
+    ctx = Context(0, Params(flags=args.flags)) if args.flags else Context(0)
     stream = torch.cuda.current_stream()
     ws = torch.empty(ctx.workspace_bytes(g.n, g.m_in), dtype=torch.uint8, device=dev)
     pv = torch.empty(g.n, dtype=torch.int64, device=dev) if per_vertex else None
@@ -348,6 +351,7 @@ def main():
     tot2 = int(graph.total_dev.item())
     assert tot2 == total, (tot2, total)
     shards = run_shards(args, ctx, graph, info, total, per_vertex) if args.shards > 1 else None
+    collisions = graph.collisions(per_vertex=per_vertex) if args.collisions else None
     ctx.timing(False)
     kernel_ms = float(np.mean(kms))
     log(f"[bench] count kernel {kernel_ms:.3f} ms (min {min(kms):.3f}), build {np.mean(build_ms):.3f} ms, "
@@ -377,6 +381,9 @@ def main():
                      "algorithmic_bytes": b_alg,
                      "kernel_source_sha1": kernel_source_sha1()},
     }
+    if collisions:
+        out["collisions"] = collisions
+        log(f"[bench] collisions: {collisions}")
     if shards:
         out["workload_partitions"] = shards
         log(f"[bench] shards: {shards}")

@@ -71,6 +71,11 @@ typedef struct tc_params {
                                    of the default stable radix sort of the oriented edges by row */
 #define TC_F_WIDE_ADDR  0x10u   /* 64-bit list addressing even below 2^30 edges (tests) */
 #define TC_F_FORCE_BIG  0x20u   /* every vertex goes to the large-LDS-table bin (tests) */
+/* Vertex order used as the hash ids (paper Section 4.1, reordering; the orientation stays the
+ * (degree, id) one).  Default: the (degree, id) rank.  At most one of: */
+#define TC_F_ORDER_INDEGREE   0x40u  /* continuous ids by oriented in-degree, largest first */
+#define TC_F_ORDER_COLLECTIVE 0x80u  /* vertices by collective degree W(u), largest first, give their
+                                        not-yet-numbered out-neighbours the next ids in list order */
 
 /* Opaque handles. */
 typedef struct tc_context tc_context;
@@ -196,6 +201,22 @@ tc_status tc_graph_count_each(tc_context* ctx, const tc_graph* g, uint64_t* d_to
 tc_status tc_graph_count_shard(tc_context* ctx, const tc_graph* g, uint32_t shard, uint32_t shards,
                                uint64_t* d_totals, uint64_t* d_per_vertex, void* d_scratch, uint64_t scratch_bytes,
                                void* stream);
+
+/* Collision statistics of the hash tables a count of g builds (paper Section
+ * 4.1, Equation 2): for every vertex with a table, the bucket count is the
+ * one the count kernels use (per-vertex mode sizes tables differently, hence
+ * the flag) and max collision(u) is the largest number of out-neighbours of
+ * u sharing a home bucket.  A diagnostic (e.g. for comparing vertex orders or
+ * hash kinds); counts are not touched.  Uses d_scratch as tc_graph_count
+ * does; synchronous on `stream`. */
+typedef struct tc_collision_stats {
+    uint64_t phi;               /* sum over tables of W(u) * max collision(u), W(u) = sum of d+(v), v in N+(u) */
+    uint64_t sum_max_collision; /* sum over tables of max collision(u) */
+    uint64_t tables;            /* vertices with a table (d+ >= 2 and W(u) > 0) */
+    uint64_t max_collision;     /* largest max collision(u) */
+} tc_collision_stats;
+tc_status tc_graph_collisions(tc_context* ctx, const tc_graph* g, int per_vertex, void* d_scratch,
+                              uint64_t scratch_bytes, void* stream, tc_collision_stats* out);
 
 /* As tc_graph_count_each, but the device work (the clears, the count
  * kernel and the per-vertex gather) is captured once into a HIP graph on a

@@ -86,8 +86,9 @@ tc_status check_params(const tc_params* p) {
     if (p->hash_kind > 1) return TC_E_INVALID;
     if (p->light_chunk < 1 || p->light_chunk > 256) return TC_E_INVALID;
     if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SCATTER_CSR | TC_F_WIDE_ADDR |
-                     TC_F_FORCE_BIG))
+                     TC_F_FORCE_BIG | TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE))
         return TC_E_INVALID;
+    if ((p->flags & TC_F_ORDER_INDEGREE) && (p->flags & TC_F_ORDER_COLLECTIVE)) return TC_E_INVALID;
     return TC_OK;
 }
 
@@ -108,6 +109,7 @@ tc::BinCaps bin_caps(const tc_context* ctx, const tc_params& p) {
     c.force_big = (p.flags & TC_F_FORCE_BIG) != 0;
     c.lpt = (p.flags & TC_F_NO_LPT) == 0;
     c.scatter_csr = (p.flags & TC_F_SCATTER_CSR) != 0;
+    c.order = (p.flags & TC_F_ORDER_INDEGREE) ? 1u : (p.flags & TC_F_ORDER_COLLECTIVE) ? 2u : 0u;
     return c;
 }
 
@@ -140,6 +142,11 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     L.t_order = o;  o = align_up(o + 4 * (size_t)n);
     L.t_skey_a = o; o = align_up(o + 8 * (size_t)n);
     L.t_skey_b = o; o = align_up(o + 8 * (size_t)n);
+    const bool relabel = (p.flags & (TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE)) != 0;
+    L.relabel = relabel;
+    L.t_rk_a = o;   o = align_up(o + (relabel ? 8 * (size_t)n : 0));
+    L.t_rk_b = o;   o = align_up(o + (relabel ? 8 * (size_t)n : 0));
+    L.t_off2 = o;   o = align_up(o + (relabel ? 8 * ((size_t)n + 1) : 0));
     L.sort_tmp_bytes = align_up(tc::prep_sort_tmp_bytes(n, m_in));
     L.t_sort = o;   o = align_up(o + L.sort_tmp_bytes);
     L.temp = o;
@@ -180,6 +187,10 @@ tc::BuildTemp temp_ptrs(void* temp, const Layout& L) {
     t.order = reinterpret_cast<uint32_t*>(b + L.t_order);
     t.skey_a = reinterpret_cast<unsigned long long*>(b + L.t_skey_a);
     t.skey_b = reinterpret_cast<unsigned long long*>(b + L.t_skey_b);
+    const bool relabel = L.relabel;
+    t.rk_a = relabel ? reinterpret_cast<unsigned long long*>(b + L.t_rk_a) : nullptr;
+    t.rk_b = relabel ? reinterpret_cast<unsigned long long*>(b + L.t_rk_b) : nullptr;
+    t.off2 = relabel ? reinterpret_cast<int64_t*>(b + L.t_off2) : nullptr;
     t.sort_tmp = b + L.t_sort;
     t.sort_tmp_bytes = L.sort_tmp_bytes;
     return t;
@@ -606,6 +617,42 @@ tc_status tc_graph_count_shard(tc_context* ctx, const tc_graph* g, uint32_t shar
     if (tc_status s = use_device(ctx)) return s;
     return count_into(ctx, g, d_totals, d_per_vertex, d_scratch, L, static_cast<hipStream_t>(stream), true, shard,
                       shards);
+}
+
+tc_status tc_graph_collisions(tc_context* ctx, const tc_graph* g, int per_vertex, void* d_scratch,
+                              uint64_t scratch_bytes, void* stream, tc_collision_stats* out) {
+    if (!ctx || !g || !out) return TC_E_INVALID;
+    std::memset(out, 0, sizeof(*out));
+    ctx->err.clear();
+    if (g->empty) return TC_OK;
+    const Layout L = layout(ctx, g->p, g->n, g->m_in, g->batch);
+    if (!d_scratch || scratch_bytes < L.scratch) return fail(ctx, TC_E_NOMEM, "scratch too small");
+    if (tc_status s = use_device(ctx)) return s;
+    const tc_params& p = g->p;
+    tc::DiagArgs a{};
+    a.meta = g->dev.meta;
+    a.off = g->dev.off;
+    a.col = g->dev.col;
+    a.items = g->dev.items;
+    a.avail[0] = (uint32_t)L.hub_words;
+    a.avail[1] = ctx->big_lds_bytes / 4;
+    a.avail[2] = p.wg_lds_bytes / 4;
+    a.avail[3] = slice_words(p);
+    a.S = p.slots_per_bucket;
+    a.lrecip = tc::load_recip(p.load_factor_pct);
+    a.hash_kind = p.hash_kind;
+    a.pv = per_vertex ? 1u : 0u;
+    a.stats = reinterpret_cast<unsigned long long*>(static_cast<char*>(d_scratch) + L.c_heads);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(ctx, tc::collision_stats(a, ctx->cu_count, s));
+    unsigned long long h[4];
+    HIP_TRY(ctx, hipMemcpyAsync(h, a.stats, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    out->phi = h[0];
+    out->sum_max_collision = h[1];
+    out->tables = h[2];
+    out->max_collision = h[3];
+    return TC_OK;
 }
 
 tc_status tc_graph_count_each(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex,

@@ -59,12 +59,6 @@ __device__ __forceinline__ void group_sync() {
     else wave_sync();
 }
 
-template <int HK>
-__device__ __forceinline__ uint32_t hash_of(uint32_t w, uint32_t B) {
-    if constexpr (HK == 0) return w & (B - 1);
-    else return (uint32_t)(((uint64_t)(w * 0x9E3779B1u) * B) >> 32);
-}
-
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 

@@ -42,6 +42,14 @@ struct Geometry {
     uint32_t B, mask, o_len, o_P, o_tslot, o_tally, words;
 };
 
+// Bucket of element w in a table of B (power of two) buckets: kind 0 takes the low bits of the id
+// (ids are degree ranks), kind 1 a multiplicative (Fibonacci) hash.
+template <int HK>
+__device__ __forceinline__ uint32_t hash_of(uint32_t w, uint32_t B) {
+    if constexpr (HK == 0) return w & (B - 1);
+    else return (uint32_t)(((uint64_t)(w * 0x9E3779B1u) * B) >> 32);
+}
+
 // Smallest power of two >= x, and largest power of two <= x (0 for x = 0).
 __host__ __device__ inline uint32_t pow2_ceil(uint32_t x) { return x <= 1 ? 1u : 1u << (32 - __builtin_clz(x - 1)); }
 __host__ __device__ inline uint32_t pow2_floor(uint32_t x) { return x ? 1u << (31 - __builtin_clz(x)) : 0u; }
@@ -127,6 +135,10 @@ struct BuildTemp {
     uint32_t* order;     // [n]
     unsigned long long* skey_a;  // [n]
     unsigned long long* skey_b;  // [n]
+    // relabelling (vertex orders other than the rank; null otherwise)
+    unsigned long long* rk_a;    // [n]
+    unsigned long long* rk_b;    // [n]
+    int64_t* off2;               // [n + 1]
     void* sort_tmp;
     size_t sort_tmp_bytes;
 };
@@ -134,6 +146,7 @@ struct BuildTemp {
 struct BinCaps {
     uint32_t wave_cap, wg_cap, big_cap;
     bool force_wg, force_hub, force_big, lpt, scatter_csr;
+    uint32_t order;  // hash-id order: 0 (degree, id) rank, 1 in-degree, 2 collective degree
 };
 
 struct Layout {
@@ -141,8 +154,9 @@ struct Layout {
     // storage offsets
     size_t s_meta, s_off, s_col, s_rank, s_items, s_gid;
     // temp offsets
-    size_t t_keys_a, t_keys_b, t_aux, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_sort;
+    size_t t_keys_a, t_keys_b, t_aux, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_rk_a, t_rk_b, t_off2, t_sort;
     size_t sort_tmp_bytes;
+    bool relabel;  // temp holds the relabelling arrays
     // scratch offsets
     size_t c_tv, c_heads, c_total, c_hub;
     uint64_t hub_words;
@@ -178,6 +192,20 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
 hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream);
 hipError_t gather_per_vertex(const unsigned long long* tv_rank, const uint32_t* rank, uint32_t n,
                              unsigned long long* out, hipStream_t stream);
+
+// tc_diag.hip: per-table collision statistics of a built graph (the cost model of Equation 2) for
+// the tables the count kernels build; avail[bin] = table words of bins 0-3.  stats = {phi,
+// sum of max collisions, tables, largest collision} (zeroed here).
+struct DiagArgs {
+    const GraphMeta* meta;
+    const int64_t* off;
+    const uint32_t* col;
+    const uint32_t* items;
+    uint32_t avail[4];
+    uint32_t S, lrecip, hash_kind, pv;
+    unsigned long long* stats;
+};
+hipError_t collision_stats(const DiagArgs& a, int cu_count, hipStream_t stream);
 
 // tc_count.hip.  `hub` selects the large-vertex kernel (bins 0 and 1) instead of the main one.
 hipError_t count_kernel_info(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,

@@ -304,6 +304,81 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
     }
 }
 
+// ---- vertex orders for the hash ids (Section 4.1, reordering)
+
+// In-degree order: larger oriented in-degree d-(r) = deg(r) - d+(r) first, ties by rank.
+__global__ void k_key_indegree(const uint32_t* __restrict__ deg_sorted, const uint32_t* __restrict__ dplus,
+                               uint32_t n, unsigned long long* __restrict__ key) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const uint32_t din = deg_sorted[r] - dplus[r];
+        key[r] = ((unsigned long long)(0xFFFFFFFFu - din) << 32) | r;
+    }
+}
+
+// Collective degree W(r) (from the inclusive scan of d+(col[e])), larger first, ties by rank.
+__global__ void k_key_collective(const int64_t* __restrict__ off, const unsigned long long* __restrict__ wscan,
+                                 uint32_t n, unsigned long long* __restrict__ key) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int64_t b = off[r], e = off[r + 1];
+        unsigned long long w = e > b ? wscan[e - 1] - (b ? wscan[b - 1] : 0ull) : 0ull;
+        if (w > 0xFFFFFFFFull) w = 0xFFFFFFFFull;
+        key[r] = ((0xFFFFFFFFull - w) << 32) | r;
+    }
+}
+
+// Greedy numbering of the collective order, in parallel: vertices taken in W order hand the next ids
+// to their not-yet-numbered out-neighbours in list order, so v's id follows its first claim, the
+// smallest (position of u in W order, position of v in u's list) over its in-edges u -> v.
+// One wavefront per row.
+__global__ void k_claim(const int64_t* __restrict__ off, const uint32_t* __restrict__ col,
+                        const uint32_t* __restrict__ posw, uint32_t n, unsigned long long* __restrict__ claim) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nwv = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < n; r += nwv) {
+        const int64_t b = off[r];
+        const uint32_t d = (uint32_t)(off[r + 1] - b);
+        const unsigned long long hi = (unsigned long long)posw[r] << 32;
+        for (uint32_t j = lane; j < d; j += 64) atomicMin(&claim[col[b + j]], hi | j);
+    }
+}
+
+// Unclaimed vertices (no in-edges) follow every claimed one, by rank.
+__global__ void k_key_claimed(uint32_t n, unsigned long long* __restrict__ claim) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        if (claim[r] == ~0ull) claim[r] = (0xFFFFFFFFull << 32) | r;
+}
+
+__global__ void k_perm_dplus(const uint32_t* __restrict__ dplus, const uint32_t* __restrict__ pi, uint32_t n,
+                             uint32_t* __restrict__ nd) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        nd[pi[r]] = dplus[r];
+        if (r == 0) nd[n] = 0;
+    }
+}
+
+// Row r of the CSR becomes row pi[r] with every entry v mapped to pi[v].  One wavefront per row.
+__global__ void k_relabel_rows(const int64_t* __restrict__ off, const uint32_t* __restrict__ col,
+                               const uint32_t* __restrict__ pi, const int64_t* __restrict__ off2, uint32_t n,
+                               uint32_t* __restrict__ col2) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nwv = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < n; r += nwv) {
+        const int64_t b = off[r];
+        const uint32_t d = (uint32_t)(off[r + 1] - b);
+        const int64_t b2 = off2[pi[r]];
+        for (uint32_t j = lane; j < d; j += 64) col2[b2 + j] = pi[col[b + j]];
+    }
+}
+
+__global__ void k_compose(uint32_t* __restrict__ rank, const uint32_t* __restrict__ pi, uint32_t n) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) rank[x] = pi[rank[x]];
+}
+
+__global__ void k_scatter_u32(const uint32_t* __restrict__ in, const uint32_t* __restrict__ pi, uint32_t n,
+                              uint32_t* __restrict__ out) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) out[pi[r]] = in[r];
+}
+
 __global__ void k_gather(const unsigned long long* __restrict__ tv, const uint32_t* __restrict__ rank, uint32_t n,
                          unsigned long long* __restrict__ out) {
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x)
@@ -356,6 +431,11 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
                 hipSuccess && sz > best) best = sz;
         sz = 0;
     }
+    {
+        size_t q = 0;
+        if (rocprim::radix_sort_pairs(nullptr, q, k64, k64, rocprim::counting_iterator<uint32_t>(0), u32p, (size_t)n, 0,
+                                      64) == hipSuccess && q > best) best = q;
+    }
     int64_t* i64p = nullptr;
     if (rocprim::exclusive_scan(nullptr, sz, u32p, i64p, (unsigned long long)0, (size_t)n + 1,
                                 rocprim::plus<unsigned long long>()) == hipSuccess && sz > best) best = sz;
@@ -363,6 +443,64 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
     if (rocprim::radix_sort_pairs(nullptr, sz, k64, k64, rocprim::counting_iterator<uint32_t>(0), u32p,
                                   (size_t)n, 0, 42) == hipSuccess && sz > best) best = sz;
     return best;
+}
+
+// Relabel the oriented rank-space CSR into another order of hash ids (the orientation stays).
+hipError_t relabel(uint32_t n, const GraphDev& g, const BuildTemp& t, const BatchIn* batch, uint32_t order,
+                   uint64_t m_in, hipStream_t stream) {
+    size_t tmp;
+    const uint32_t wave_grid = std::min<uint32_t>(grid_for((uint64_t)n * 64), 8192u);
+    if (order == 1) {
+        hipLaunchKernelGGL(k_key_indegree, dim3(grid_for(n)), dim3(kThreads), 0, stream,
+                           reinterpret_cast<const uint32_t*>(t.skey_a), t.dplus, n, t.rk_a);
+        TC_TRY(hipGetLastError());
+    } else {
+        unsigned long long* wscan = t.keys_a;
+        auto heads = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
+                                                      HeadOutDegree{g.col, t.dplus, g.meta});
+        tmp = t.sort_tmp_bytes;
+        TC_TRY(rocprim::inclusive_scan(t.sort_tmp, tmp, heads, wscan, (size_t)m_in,
+                                       rocprim::plus<unsigned long long>(), stream));
+        hipLaunchKernelGGL(k_key_collective, dim3(grid_for(n)), dim3(kThreads), 0, stream, g.off, wscan, n, t.rk_a);
+        TC_TRY(hipGetLastError());
+        tmp = t.sort_tmp_bytes;
+        TC_TRY(rocprim::radix_sort_pairs(t.sort_tmp, tmp, t.rk_a, t.rk_b, rocprim::counting_iterator<uint32_t>(0),
+                                         t.order, (size_t)n, 0, 64, stream));
+        uint32_t* posw = reinterpret_cast<uint32_t*>(t.skey_b);
+        hipLaunchKernelGGL(k_rank, dim3(grid_for(n)), dim3(kThreads), 0, stream, t.order, n, posw);
+        TC_TRY(hipGetLastError());
+        TC_TRY(fill_u32(t.rk_a, 0xFFFFFFFFu, 2 * (size_t)n, stream));
+        hipLaunchKernelGGL(k_claim, dim3(wave_grid), dim3(kThreads), 0, stream, g.off, g.col, posw, n, t.rk_a);
+        TC_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_key_claimed, dim3(grid_for(n)), dim3(kThreads), 0, stream, n, t.rk_a);
+        TC_TRY(hipGetLastError());
+    }
+    tmp = t.sort_tmp_bytes;
+    TC_TRY(rocprim::radix_sort_pairs(t.sort_tmp, tmp, t.rk_a, t.rk_b, rocprim::counting_iterator<uint32_t>(0),
+                                     t.order, (size_t)n, 0, 64, stream));
+    uint32_t* pi = t.deg;  // new id of every rank
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(n)), dim3(kThreads), 0, stream, t.order, n, pi);
+    TC_TRY(hipGetLastError());
+    uint32_t* nd = reinterpret_cast<uint32_t*>(t.skey_b);  // out-degrees by new id, [n + 1]
+    hipLaunchKernelGGL(k_perm_dplus, dim3(grid_for(n)), dim3(kThreads), 0, stream, t.dplus, pi, n, nd);
+    TC_TRY(hipGetLastError());
+    tmp = t.sort_tmp_bytes;
+    TC_TRY(rocprim::exclusive_scan(t.sort_tmp, tmp, nd, t.off2, (unsigned long long)0, (size_t)n + 1,
+                                   rocprim::plus<unsigned long long>(), stream));
+    uint32_t* col2 = reinterpret_cast<uint32_t*>(t.keys_b);
+    hipLaunchKernelGGL(k_relabel_rows, dim3(wave_grid), dim3(kThreads), 0, stream, g.off, g.col, pi, t.off2, n, col2);
+    TC_TRY(hipGetLastError());
+    TC_TRY(hipMemcpyAsync(g.col, col2, 4 * (size_t)m_in, hipMemcpyDeviceToDevice, stream));
+    TC_TRY(hipMemcpyAsync(g.off, t.off2, 8 * ((size_t)n + 1), hipMemcpyDeviceToDevice, stream));
+    TC_TRY(hipMemcpyAsync(t.dplus, nd, 4 * ((size_t)n + 1), hipMemcpyDeviceToDevice, stream));
+    hipLaunchKernelGGL(k_compose, dim3(grid_for(n)), dim3(kThreads), 0, stream, g.rank, pi, n);
+    TC_TRY(hipGetLastError());
+    if (batch) {
+        TC_TRY(hipMemcpyAsync(t.order, g.gid, 4 * (size_t)n, hipMemcpyDeviceToDevice, stream));
+        hipLaunchKernelGGL(k_scatter_u32, dim3(grid_for(n)), dim3(kThreads), 0, stream, t.order, pi, n, g.gid);
+        TC_TRY(hipGetLastError());
+    }
+    return hipSuccess;
 }
 
 hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint32_t* dst, const GraphDev& g,
@@ -459,6 +597,9 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
                            sentinel, g.rank, g.off, t.deg, g.col);
         TC_TRY(hipGetLastError());
     }
+
+    // 5b (optional): hash ids in another vertex order.
+    if (caps.order) TC_TRY(relabel(n, g, t, batch, caps.order, m_in, stream));
 
     // 6: bins and largest-work-first order; W(u) from a scan of d+(col[e]).
     unsigned long long* wscan = reinterpret_cast<unsigned long long*>(t.keys_a);

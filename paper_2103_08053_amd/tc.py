@@ -22,7 +22,7 @@ EXPORTS = [
     "tc_last_error", "tc_workspace_bytes", "tc_count", "tc_graph_footprint", "tc_graph_build",
     "tc_count_scratch_bytes", "tc_graph_count", "tc_graph_info_get", "tc_graph_release",
     "tc_timing_enable", "tc_timing_last", "tc_batch_footprint", "tc_batch_build", "tc_graph_count_each",
-    "tc_graph_count_replay", "tc_graph_k", "tc_graph_count_shard",
+    "tc_graph_count_replay", "tc_graph_k", "tc_graph_count_shard", "tc_graph_collisions",
 ]
 
 
@@ -40,6 +40,11 @@ class _Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "struct_size", "wg_waves", "wg_lds_bytes", "wave_max_dplus", "slots_per_bucket", "load_factor_pct",
         "hash_kind", "light_chunk", "grid_wgs", "flags")]
+
+
+class _CollisionStats(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_uint64), ("sum_max_collision", ctypes.c_uint64), ("tables", ctypes.c_uint64),
+                ("max_collision", ctypes.c_uint64)]
 
 
 class _GraphInfo(ctypes.Structure):
@@ -122,6 +127,7 @@ def load_library(path: str = LIB_PATH):
         "tc_graph_count_each": [vp, vp, vp, vp, vp, u64, vp],
         "tc_graph_count_replay": [vp, vp, vp, vp, vp, u64, vp],
         "tc_graph_count_shard": [vp, vp, u32, u32, vp, vp, vp, u64, vp],
+        "tc_graph_collisions": [vp, vp, i32, vp, u64, vp, ctypes.POINTER(_CollisionStats)],
         "tc_graph_k": [vp, ctypes.POINTER(u32)],
         "tc_timing_last": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
     }
@@ -333,6 +339,14 @@ class Graph:
         self.count_async(pv, stream, replay=replay, shard=shard)
         tot = self.totals_dev.cpu().tolist()
         return (tot[0] if self.k == 1 else tot), (pv[: self.n] if per_vertex else None)
+
+    def collisions(self, per_vertex: bool = True, stream=None) -> dict:
+        """Collision statistics of the tables a count builds (Equation 2's phi and friends)."""
+        st = _CollisionStats()
+        _check(self.ctx.lib.tc_graph_collisions(self.ctx.h, self.h, int(per_vertex), _ptr(self.scratch),
+                                                self.scratch.numel(), _stream_ptr(stream), ctypes.byref(st)),
+               self.ctx.h)
+        return {k: int(getattr(st, k)) for k, _ in _CollisionStats._fields_}
 
     def release(self):
         if getattr(self, "h", None):

@@ -106,6 +106,8 @@ FORCED = [
     dict(flags=2),                              # every vertex in the workgroup bin
     dict(flags=4),                              # every vertex in the global-memory table bin
     dict(flags=32),                             # every vertex in the large-LDS bin
+    dict(flags=0x40), dict(flags=0x80),         # hash ids in in-degree / collective-degree order
+    dict(flags=0x80 | 4, slots_per_bucket=1, load_factor_pct=100),
     dict(wg_lds_bytes=4096, wg_waves=4),        # tiny LDS: most vertices spill to the global-table bin
     dict(slots_per_bucket=1), dict(slots_per_bucket=4),
     dict(load_factor_pct=100), dict(load_factor_pct=10),
@@ -313,3 +315,40 @@ def test_shard_arguments_checked(ctx, torch):
     for bad in ((0, 0), (3, 3), (5, 2)):
         with pytest.raises(TCError):
             graph.count(shard=bad)
+
+
+# ----------------------------------------------------------------------------- collision statistics
+
+def test_collision_stats_complete_graph(ctx, torch):
+    """K_100: N+(u) is a run of consecutive ranks and (default knobs, d+ < 100) every table has
+    B >= d+ buckets, so with the low-bits hash no two out-neighbours share a home bucket: max
+    collision 1 everywhere and phi (Equation 2) = W+."""
+    g = gg.complete(100)
+    graph = ctx.build(g.src, g.dst, g.n)
+    info = graph.info()
+    for pv in (True, False):
+        st = graph.collisions(per_vertex=pv)
+        assert st["tables"] == g.n - 2 == info.n_wave + info.n_wg + info.n_big + info.n_hub
+        assert st["max_collision"] == 1 and st["sum_max_collision"] == st["tables"]
+        assert st["phi"] == info.wedges_plus
+
+
+def test_collision_stats_bounds(torch):
+    """On a skewed graph: 1 <= max collision(u), so phi >= W+ of the tabled vertices and the sum of
+    maxima >= tables; a full one-slot table at 100% load cannot collide less than a 10% one."""
+    from paper_2103_08053_amd import Context, Params
+    g = gg.dirty(gg.rmat(13, 16, seed=7), seed=8)
+    lo = Context(0, Params(load_factor_pct=10, slots_per_bucket=1, wave_max_dplus=0)).build(g.src, g.dst, g.n)
+    hi = Context(0, Params(load_factor_pct=100, slots_per_bucket=1)).build(g.src, g.dst, g.n)
+    a, b = lo.collisions(), hi.collisions()
+    for st, gr in ((a, lo), (b, hi)):
+        info = gr.info()
+        assert st["tables"] == info.n_wave + info.n_wg + info.n_big + info.n_hub
+        assert st["sum_max_collision"] >= st["tables"] and st["max_collision"] >= 1
+        assert st["phi"] >= st["sum_max_collision"]
+    assert b["sum_max_collision"] >= a["sum_max_collision"]
+    for order in (0x40, 0x80):  # other vertex orders: same tables, same counts
+        c = Context(0, Params(flags=order))
+        gr = c.build(g.src, g.dst, g.n)
+        assert gr.collisions()["tables"] == a["tables"]
+        assert gr.count()[0] == oracle.count(g.n, g.src, g.dst).total

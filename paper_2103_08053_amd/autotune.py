@@ -5,9 +5,17 @@ checks that on every candidate (a differing count raises).  Search is
 coordinate descent from the defaults: each knob in turn is set to each of
 its candidate values while the others stay at the best so far, keeping any
 strict improvement of the measured count-kernel time (HIP events recorded by
-the library around the persistent launch, median of `trials` launches).  Two
+the library around the count launches, median of `trials` launches).  Two
 passes over the knobs.  Because knobs that size the tables or the bins are
 fixed when a graph is built, each candidate rebuilds the graph (or batch).
+
+Prior: the cost estimate of the paper's Equation 2, phi = sum over vertices
+of W(u) * max collision(u), computed by the library for the tables a
+candidate builds (tc_graph_collisions).  Candidates of the knobs that decide
+the tables (slots per bucket, load factor, hash kind, vertex order) whose phi
+exceeds `prior_ratio` times the current best's are rejected without timing.
+The knob "order" is the hash-id vertex order (Section 4.1): 0 (degree rank),
+0x40 (in-degree), 0x80 (collective degree), set in the flags.
 
 Results are cached in a JSON file keyed by coarse features of the workload
 (log2 of n, m, the largest out-degree and the mean 2-hop list length W+/m,
@@ -32,7 +40,20 @@ SPACE = {
     "light_chunk": [1, 2, 4, 8, 16],
     "hash_kind": [0, 1],
     "wave_max_dplus": [0, 32, 64, 128],
+    "order": [0, 0x40, 0x80],
 }
+TABLE_KNOBS = ("slots_per_bucket", "load_factor_pct", "hash_kind", "order")
+ORDER_BITS = 0x40 | 0x80
+
+
+def _with(p: Params, knob: str, v) -> Params:
+    if knob == "order":
+        return replace(p, flags=(p.flags & ~ORDER_BITS) | v)
+    return replace(p, **{knob: v})
+
+
+def _get(p: Params, knob: str):
+    return p.flags & ORDER_BITS if knob == "order" else getattr(p, knob)
 
 
 def default_cache_path() -> str:
@@ -60,7 +81,8 @@ class _Workload:
         self.batch = batch
         self.per_vertex = per_vertex
 
-    def measure(self, params: Params, trials: int):
+    def measure(self, params: Params, trials: int, phi_limit: float | None = None):
+        """(median ms, totals, info, k, phi); ms and totals are None when phi exceeds phi_limit."""
         import torch
         ctx = Context(self.device, params)
         if self.batch:
@@ -68,6 +90,12 @@ class _Workload:
         else:
             src, dst, n = self.graph_args
             g = Graph(ctx, src, dst, n)
+        phi = g.collisions(per_vertex=self.per_vertex)["phi"]
+        if phi_limit is not None and phi > phi_limit:
+            info, k = g.info(), g.k
+            g.release()
+            ctx.close()
+            return None, None, info, k, phi
         pv = torch.empty(max(g.n, 1), dtype=torch.int64, device=g.storage.device) if self.per_vertex else None
         ctx.timing(True)
         g.count_async(pv)  # warm-up (first launch resolves the launch shape)
@@ -82,12 +110,12 @@ class _Workload:
         g.release()
         ctx.close()
         times.sort()
-        return times[len(times) // 2], totals, info, k
+        return times[len(times) // 2], totals, info, k, phi
 
 
 def tune(graph_args, batch: bool = False, per_vertex: bool = False, device: int = 0, trials: int = 3,
          space: dict | None = None, passes: int = 2, start: Params | None = None, cache_path: str | None = None,
-         use_cache: bool = True, verbose: bool = False):
+         use_cache: bool = True, verbose: bool = False, prior_ratio: float = 1.5):
     """Tune the knobs for one workload.
 
     graph_args: (src, dst, n) for a single graph, or a list of (n_g, src_g, dst_g)
@@ -96,39 +124,47 @@ def tune(graph_args, batch: bool = False, per_vertex: bool = False, device: int 
     wl = _Workload(device, graph_args, batch, per_vertex)
     best = start or Params()
     t0 = time.time()
-    best_ms, ref, info, k = wl.measure(best, trials)
+    best_ms, ref, info, k, best_phi = wl.measure(best, trials)
     key = feature_key(info, per_vertex, k)
     cache_path = cache_path or default_cache_path()
     if use_cache and os.path.exists(cache_path):
         cached = json.load(open(cache_path)).get(key)
         if cached:
             p = Params(**cached["params"])
-            ms, tot, _, _ = wl.measure(p, trials)
+            ms, tot, _, _, _ = wl.measure(p, trials)
             if tot != ref:
                 raise AssertionError(f"cached params changed the count: {tot} vs {ref}")
             return p, {"key": key, "cached": True, "ms": ms, "default_ms": best_ms}
-    history = [(asdict(best), best_ms)]
+    history = [(asdict(best), best_ms, best_phi)]
+    skipped = 0
     for _ in range(passes):
         improved = False
         for knob, values in space.items():
             for v in values:
-                if getattr(best, knob) == v:
+                if _get(best, knob) == v:
                     continue
-                cand = replace(best, **{knob: v})
+                cand = _with(best, knob, v)
                 if not _valid(cand):
                     continue
-                ms, tot, _, _ = wl.measure(cand, trials)
+                limit = prior_ratio * best_phi if knob in TABLE_KNOBS else None
+                ms, tot, _, _, phi = wl.measure(cand, trials, limit)
+                if ms is None:
+                    skipped += 1
+                    if verbose:
+                        print(f"[tune] {knob}={v}: phi {phi:.4g} > {limit:.4g}, not timed", flush=True)
+                    continue
                 if tot != ref:
                     raise AssertionError(f"{knob}={v} changed the count: {tot} vs {ref}")
-                history.append((asdict(cand), ms))
+                history.append((asdict(cand), ms, phi))
                 if verbose:
-                    print(f"[tune] {knob}={v}: {ms:.3f} ms (best {best_ms:.3f})", flush=True)
+                    print(f"[tune] {knob}={v}: {ms:.3f} ms phi {phi:.4g} (best {best_ms:.3f})", flush=True)
                 if ms < best_ms * 0.995:
-                    best, best_ms, improved = cand, ms, True
+                    best, best_ms, best_phi, improved = cand, ms, phi, True
         if not improved:
             break
     report = {"key": key, "cached": False, "ms": best_ms, "default_ms": history[0][1],
-              "params": asdict(best), "evaluated": len(history), "seconds": round(time.time() - t0, 1)}
+              "params": asdict(best), "evaluated": len(history), "skipped_by_prior": skipped,
+              "phi": best_phi, "default_phi": history[0][2], "seconds": round(time.time() - t0, 1)}
     if use_cache:
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         data = json.load(open(cache_path)) if os.path.exists(cache_path) else {}

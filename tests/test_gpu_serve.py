@@ -56,3 +56,15 @@ def test_autotune_keeps_counts(tmp_path):
     assert Context(0, p).count(g.src, g.dst, g.n)[0] == Context(0).count(g.src, g.dst, g.n)[0]
     p2, rep2 = autotune.tune((g.src, g.dst, g.n), space=space, cache_path=str(tmp_path / "t.json"))
     assert rep2["cached"] and p2 == p
+
+
+def test_autotune_prior_rejects_without_timing(tmp_path):
+    """Table knobs whose Equation 2 estimate exceeds the ratio are not timed; others are."""
+    from paper_2103_08053_amd import autotune
+    g = gg.rmat(12, 16, seed=3)
+    space = {"load_factor_pct": [10, 100], "order": [0x40], "light_chunk": [2]}
+    p, rep = autotune.tune((g.src, g.dst, g.n), space=space, passes=1, trials=2, use_cache=False,
+                           prior_ratio=1e-3)
+    say(f"[gpu] tuned {rep}")
+    assert rep["skipped_by_prior"] == 3 and rep["evaluated"] == 2  # default + light_chunk=2
+    assert rep["phi"] > 0 and rep["default_phi"] > 0

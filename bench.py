@@ -282,6 +282,8 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="extra TC_F_* flags for the single-graph workloads "
                     "(e.g. 64: in-degree vertex order, 128: collective-degree order)")
     ap.add_argument("--collisions", action="store_true", help="also report the tables' collision statistics")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also time the plain vertex- and edge-centric designs (full and tables only)")
     ap.add_argument("--shards", type=int, default=0,
                     help="with a single-graph workload: also time its count as this many workload partitions")
     args = ap.parse_args()
@@ -352,6 +354,22 @@ def main():
     assert tot2 == total, (tot2, total)
     shards = run_shards(args, ctx, graph, info, total, per_vertex) if args.shards > 1 else None
     collisions = graph.collisions(per_vertex=per_vertex) if args.collisions else None
+    ablation = None
+    if args.ablation:
+        ablation = {}
+        for name, edge, build_only in (("vertex_centric", False, False), ("edge_centric", True, False),
+                                       ("vertex_centric_tables_only", False, True),
+                                       ("edge_centric_tables_only", True, True)):
+            t_ = graph.count_simple(edge_centric=edge, build_only=build_only)
+            assert t_ == (0 if build_only else total), (name, t_, total)
+            ablation[name + "_ms"] = ctx.last_times_ms()[1]
+            log(f"[bench] ablation {name}: {ablation[name + '_ms']:.3f} ms")
+        ablation["construction_edge_over_vertex"] = (ablation["edge_centric_tables_only_ms"]
+                                                     / ablation["vertex_centric_tables_only_ms"])
+        ablation["construction_share_vertex"] = (ablation["vertex_centric_tables_only_ms"]
+                                                 / ablation["vertex_centric_ms"])
+        ablation["construction_share_edge"] = (ablation["edge_centric_tables_only_ms"]
+                                               / ablation["edge_centric_ms"])
     ctx.timing(False)
     kernel_ms = float(np.mean(kms))
     log(f"[bench] count kernel {kernel_ms:.3f} ms (min {min(kms):.3f}), build {np.mean(build_ms):.3f} ms, "
@@ -381,6 +399,8 @@ def main():
                      "algorithmic_bytes": b_alg,
                      "kernel_source_sha1": kernel_source_sha1()},
     }
+    if ablation:
+        out["design_ablation"] = ablation
     if collisions:
         out["collisions"] = collisions
         log(f"[bench] collisions: {collisions}")

@@ -218,6 +218,24 @@ typedef struct tc_collision_stats {
 tc_status tc_graph_collisions(tc_context* ctx, const tc_graph* g, int per_vertex, void* d_scratch,
                               uint64_t scratch_bytes, void* stream, tc_collision_stats* out);
 
+/* The plain designs of paper Section 3.3 on the same hash tables, for the
+ * table-construction ablation: one workgroup per vertex, lane-by-lane
+ * lookups, tables in wg_lds_bytes of LDS (all the LDS a workgroup may have
+ * when some out-degree needs it).  Mode bits:
+ *   TC_SIMPLE_EDGE_CENTRIC: Algorithm 2, the table of N+(u) is built again
+ *     for every oriented edge (u, v) (otherwise once per vertex);
+ *   TC_SIMPLE_BUILD_ONLY: tables only, no intersection (the count is 0), so
+ *     the launch time is the construction time.
+ * Writes the total to d_total (device uint64) for a single graph (k = 1);
+ * TC_E_UNSUPPORTED when some out-degree does not fit the LDS table.  Uses
+ * d_scratch as tc_graph_count does.  Reads the graph summary first
+ * (synchronises `stream`), then launches asynchronously; with timing on, the
+ * launch is what tc_timing_last reports as the count. */
+#define TC_SIMPLE_EDGE_CENTRIC 0x1u
+#define TC_SIMPLE_BUILD_ONLY   0x2u
+tc_status tc_graph_count_simple(tc_context* ctx, const tc_graph* g, uint32_t mode, uint64_t* d_total,
+                                void* d_scratch, uint64_t scratch_bytes, void* stream);
+
 /* As tc_graph_count_each, but the device work (the clears, the count
  * kernel and the per-vertex gather) is captured once into a HIP graph on a
  * stream owned by ctx and replayed on `stream` by later calls with the same

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtrust_tc.so")
 OBJ = os.path.join(PKG, "_build")
-SOURCES = ["tc_abi.cpp", "tc_prep.hip", "tc_count.hip", "tc_diag.hip"]
+SOURCES = ["tc_abi.cpp", "tc_prep.hip", "tc_count.hip", "tc_diag.hip", "tc_edge.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

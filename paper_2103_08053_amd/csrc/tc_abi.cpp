@@ -655,6 +655,55 @@ tc_status tc_graph_collisions(tc_context* ctx, const tc_graph* g, int per_vertex
     return TC_OK;
 }
 
+tc_status tc_graph_count_simple(tc_context* ctx, const tc_graph* g, uint32_t mode, uint64_t* d_total,
+                                void* d_scratch, uint64_t scratch_bytes, void* stream) {
+    if (!ctx || !g || !d_total) return TC_E_INVALID;
+    if (mode & ~(TC_SIMPLE_EDGE_CENTRIC | TC_SIMPLE_BUILD_ONLY)) return fail(ctx, TC_E_INVALID, "mode %u", mode);
+    if (g->k != 1) return fail(ctx, TC_E_INVALID, "a batch of %u graphs: single graphs only", g->k);
+    ctx->err.clear();
+    const Layout L = layout(ctx, g->p, g->n, g->m_in, g->batch);
+    if (!d_scratch || scratch_bytes < L.scratch) return fail(ctx, TC_E_NOMEM, "scratch too small");
+    if (tc_status s = use_device(ctx)) return s;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->empty) {
+        HIP_TRY(ctx, tc::fill_u32(d_total, 0, 2, s));
+        return TC_OK;
+    }
+    tc::GraphMeta m;
+    HIP_TRY(ctx, hipMemcpyAsync(&m, g->dev.meta, sizeof(m), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const tc_params& p = g->p;
+    // Tables in the workgroup LDS of the count launch, or in all the LDS a workgroup may have.
+    uint32_t lds = p.wg_lds_bytes, cap = 0;
+    HIP_TRY(ctx, tc::simple_capacity(lds, p.load_factor_pct, &cap));
+    if (m.max_dplus > cap) {
+        lds = ctx->big_lds_bytes;
+        HIP_TRY(ctx, tc::simple_capacity(lds, p.load_factor_pct, &cap));
+    }
+    if (m.max_dplus > cap)
+        return fail(ctx, TC_E_UNSUPPORTED, "out-degree %u exceeds the LDS table limit %u", m.max_dplus, cap);
+    tc::SimpleArgs a{};
+    a.meta = g->dev.meta;
+    a.off = g->dev.off;
+    a.col = g->dev.col;
+    a.items = g->dev.items;
+    a.head = reinterpret_cast<uint32_t*>(static_cast<char*>(d_scratch) + L.c_heads);
+    a.total = reinterpret_cast<unsigned long long*>(d_total);
+    a.lds_words = lds / 4;
+    a.lrecip = tc::load_recip(p.load_factor_pct);
+    HIP_TRY(ctx, tc::fill_u32(a.head, 0, 1, s));
+    HIP_TRY(ctx, tc::fill_u32(d_total, 0, 2, s));
+    const bool rec = ctx->timing;
+    if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
+    HIP_TRY(ctx, tc::simple_launch((mode & TC_SIMPLE_EDGE_CENTRIC) != 0, (mode & TC_SIMPLE_BUILD_ONLY) != 0, lds,
+                                   ctx->cu_count, a, s));
+    if (rec) {
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
+        ctx->have_count = true;
+    }
+    return TC_OK;
+}
+
 tc_status tc_graph_count_each(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex,
                               void* d_scratch, uint64_t scratch_bytes, void* stream) {
     if (!ctx || !g || !d_totals) return TC_E_INVALID;

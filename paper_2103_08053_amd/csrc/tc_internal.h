@@ -207,6 +207,25 @@ struct DiagArgs {
 };
 hipError_t collision_stats(const DiagArgs& a, int cu_count, hipStream_t stream);
 
+// tc_edge.hip: the plain reference designs of Section 3.3 on the same tables, for the construction
+// ablation: vertex-centric (one table per vertex) or edge-centric (Algorithm 2: the table of N+(u)
+// rebuilt for every edge (u, v)), one workgroup per vertex, lane-by-lane lookups; optionally tables
+// only.  Tables are in LDS (lds_words); every scheduled vertex must fit.
+struct SimpleArgs {
+    const GraphMeta* meta;
+    const int64_t* off;
+    const uint32_t* col;
+    const uint32_t* items;
+    uint32_t* head;                  // [1], zeroed before the launch
+    unsigned long long* total;       // [1], zeroed before the launch
+    uint32_t lds_words, lrecip;
+};
+constexpr uint32_t kSimpleThreads = 256;
+constexpr uint32_t kSimpleS = 4;
+hipError_t simple_capacity(uint32_t lds_bytes, uint32_t load_pct, uint32_t* max_d);
+hipError_t simple_launch(bool edge, bool build_only, uint32_t lds_bytes, int cu_count, const SimpleArgs& a,
+                         hipStream_t stream);
+
 // tc_count.hip.  `hub` selects the large-vertex kernel (bins 0 and 1) instead of the main one.
 hipError_t count_kernel_info(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
                              uint32_t lds_bytes, int* blocks_per_cu);

@@ -352,3 +352,33 @@ def test_collision_stats_bounds(torch):
         gr = c.build(g.src, g.dst, g.n)
         assert gr.collisions()["tables"] == a["tables"]
         assert gr.count()[0] == oracle.count(g.n, g.src, g.dst).total
+
+
+# ----------------------------------------------------------------------------- Section 3.3 designs
+
+SIMPLE_CASES = [gg.complete(60), gg.wheel(300), gg.complete_tripartite(5, 6, 7), gg.friendship(40),
+                gg.torus3d(6), gg.dirty(gg.rmat(12, 16, seed=11), seed=12), gg.barabasi_albert(3000, 8, seed=4)]
+
+
+@pytest.mark.parametrize("g", SIMPLE_CASES, ids=[g.name for g in SIMPLE_CASES])
+def test_plain_vertex_and_edge_centric_designs(ctx, torch, g):
+    """Algorithm 1 without the optimisations and Algorithm 2 (one table per edge) count exactly;
+    table construction alone counts nothing."""
+    graph = ctx.build(g.src, g.dst, g.n)
+    want = oracle.count(g.n, g.src, g.dst).total
+    assert graph.count_simple(edge_centric=False) == want
+    assert graph.count_simple(edge_centric=True) == want
+    assert graph.count_simple(edge_centric=True, build_only=True) == 0
+    assert graph.count_simple(edge_centric=False, build_only=True) == 0
+
+
+def test_plain_designs_reject_what_they_cannot_hold(torch):
+    from paper_2103_08053_amd import Batch, Context, Params, TCError
+    c = Context(0, Params(wg_lds_bytes=4096, wg_waves=4))
+    g = gg.complete(9000)  # d+ up to 8999: beyond any LDS table
+    graph = c.build(g.src, g.dst, g.n)
+    with pytest.raises(TCError):
+        graph.count_simple()
+    b = Batch(c, [(5, gg.complete(5).src, gg.complete(5).dst)] * 2)
+    with pytest.raises(TCError):
+        b.count_simple()

@@ -282,6 +282,8 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="extra TC_F_* flags for the single-graph workloads "
                     "(e.g. 64: in-degree vertex order, 128: collective-degree order)")
     ap.add_argument("--collisions", action="store_true", help="also report the tables' collision statistics")
+    ap.add_argument("--intra", action="store_true",
+                    help="also time the count with subwave (8/16/32 lanes) and per-wavefront list assignment")
     ap.add_argument("--ablation", action="store_true",
                     help="also time the plain vertex- and edge-centric designs (full and tables only)")
     ap.add_argument("--shards", type=int, default=0,
@@ -374,6 +376,22 @@ def main():
     kernel_ms = float(np.mean(kms))
     log(f"[bench] count kernel {kernel_ms:.3f} ms (min {min(kms):.3f}), build {np.mean(build_ms):.3f} ms, "
         f"info {info}")
+    intra = None
+    if args.intra:
+        intra = {"virtual_combination_ms": kernel_ms}
+        for name, fl in (("subwave_8", 0x100), ("subwave_16", 0x200), ("subwave_32", 0x400), ("wave_per_list", 0x800)):
+            c2 = Context(0, Params(flags=args.flags | fl))
+            g2 = c2.build(src, dst, g.n)
+            c2.timing(True)
+            ms2 = []
+            for _ in range(3):
+                g2.count_async(pv)
+                ms2.append(c2.last_times_ms()[1])
+            assert int(g2.total_dev.item()) == total, name
+            intra[name + "_ms"] = sorted(ms2)[1]
+            log(f"[bench] intra {name}: {intra[name + '_ms']:.3f} ms")
+            g2.release()
+            c2.close()
 
     b_alg = algorithmic_bytes(g.n, info.m, info.wedges_plus, per_vertex)
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
@@ -401,6 +419,8 @@ def main():
     }
     if ablation:
         out["design_ablation"] = ablation
+    if intra:
+        out["intra_vertex"] = intra
     if collisions:
         out["collisions"] = collisions
         log(f"[bench] collisions: {collisions}")

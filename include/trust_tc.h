@@ -76,6 +76,12 @@ typedef struct tc_params {
 #define TC_F_ORDER_INDEGREE   0x40u  /* continuous ids by oriented in-degree, largest first */
 #define TC_F_ORDER_COLLECTIVE 0x80u  /* vertices by collective degree W(u), largest first, give their
                                         not-yet-numbered out-neighbours the next ids in list order */
+/* Intra-vertex work assignment of the probe (paper Section 4.2).  Default: virtual combination.
+ * At most one of (the build is the same; counts use the parameters the graph was built with): */
+#define TC_F_SUBWAVE_8   0x100u  /* groups of 8 lanes, one out-neighbour list per group */
+#define TC_F_SUBWAVE_16  0x200u  /* groups of 16 lanes */
+#define TC_F_SUBWAVE_32  0x400u  /* groups of 32 lanes */
+#define TC_F_WAVE_LIST   0x800u  /* one list per wavefront at a time (warp-centric) */
 
 /* Opaque handles. */
 typedef struct tc_context tc_context;

@@ -15,7 +15,9 @@ candidate builds (tc_graph_collisions).  Candidates of the knobs that decide
 the tables (slots per bucket, load factor, hash kind, vertex order) whose phi
 exceeds `prior_ratio` times the current best's are rejected without timing.
 The knob "order" is the hash-id vertex order (Section 4.1): 0 (degree rank),
-0x40 (in-degree), 0x80 (collective degree), set in the flags.
+0x40 (in-degree), 0x80 (collective degree); "intra" the intra-vertex probe
+assignment (Section 4.2): 0 (virtual combination), subwaves of 8/16/32 lanes
+(0x100/0x200/0x400) or one list per wavefront (0x800); both set in the flags.
 
 Results are cached in a JSON file keyed by coarse features of the workload
 (log2 of n, m, the largest out-degree and the mean 2-hop list length W+/m,
@@ -41,19 +43,20 @@ SPACE = {
     "hash_kind": [0, 1],
     "wave_max_dplus": [0, 32, 64, 128],
     "order": [0, 0x40, 0x80],
+    "intra": [0, 0x100, 0x200, 0x400, 0x800],
 }
 TABLE_KNOBS = ("slots_per_bucket", "load_factor_pct", "hash_kind", "order")
-ORDER_BITS = 0x40 | 0x80
+FLAG_KNOBS = {"order": 0x40 | 0x80, "intra": 0x100 | 0x200 | 0x400 | 0x800}
 
 
 def _with(p: Params, knob: str, v) -> Params:
-    if knob == "order":
-        return replace(p, flags=(p.flags & ~ORDER_BITS) | v)
+    if knob in FLAG_KNOBS:
+        return replace(p, flags=(p.flags & ~FLAG_KNOBS[knob]) | v)
     return replace(p, **{knob: v})
 
 
 def _get(p: Params, knob: str):
-    return p.flags & ORDER_BITS if knob == "order" else getattr(p, knob)
+    return p.flags & FLAG_KNOBS[knob] if knob in FLAG_KNOBS else getattr(p, knob)
 
 
 def default_cache_path() -> str:

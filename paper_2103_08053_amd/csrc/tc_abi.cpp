@@ -25,7 +25,7 @@ struct tc_context {
     bool have_build = false, have_count = false;
     hipStream_t capture_stream = nullptr;  // for tc_graph_count_replay
     struct Occ {
-        uint32_t hub, S, pv, hk, threads, lds;
+        uint32_t hub, sw, S, pv, hk, threads, lds;
         int per_cu;
     };
     std::vector<Occ> occ;  // resident workgroups per CU, by kernel variant and launch shape
@@ -77,6 +77,16 @@ tc_status hip_fail(tc_context* c, hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
     } while (0)
 
+constexpr uint32_t kIntraFlags = TC_F_SUBWAVE_8 | TC_F_SUBWAVE_16 | TC_F_SUBWAVE_32 | TC_F_WAVE_LIST;
+
+uint32_t subwave_lanes(uint32_t flags) {
+    if (flags & TC_F_SUBWAVE_8) return 8;
+    if (flags & TC_F_SUBWAVE_16) return 16;
+    if (flags & TC_F_SUBWAVE_32) return 32;
+    if (flags & TC_F_WAVE_LIST) return 64;
+    return 0;
+}
+
 tc_status check_params(const tc_params* p) {
     if (!p || p->struct_size != sizeof(tc_params)) return TC_E_INVALID;
     if (p->wg_waves < 1 || p->wg_waves > tc::kMaxWaves) return TC_E_INVALID;
@@ -86,8 +96,9 @@ tc_status check_params(const tc_params* p) {
     if (p->hash_kind > 1) return TC_E_INVALID;
     if (p->light_chunk < 1 || p->light_chunk > 256) return TC_E_INVALID;
     if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SCATTER_CSR | TC_F_WIDE_ADDR |
-                     TC_F_FORCE_BIG | TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE))
+                     TC_F_FORCE_BIG | TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE | kIntraFlags))
         return TC_E_INVALID;
+    if (__builtin_popcount(p->flags & kIntraFlags) > 1) return TC_E_INVALID;
     if ((p->flags & TC_F_ORDER_INDEGREE) && (p->flags & TC_F_ORDER_COLLECTIVE)) return TC_E_INVALID;
     return TC_OK;
 }
@@ -247,16 +258,17 @@ uint32_t launch_lds(const tc_context* ctx, const tc_params& p, bool hub) {
 
 tc_status occupancy(tc_context* ctx, const tc_params& p, bool pv, bool hub, int* per_cu) {
     const uint32_t threads = launch_threads(p, hub), lds = launch_lds(ctx, p, hub);
+    const uint32_t sw = (!hub && subwave_lanes(p.flags)) ? 1u : 0u;
     for (const auto& o : ctx->occ)
-        if (o.hub == (uint32_t)hub && o.S == p.slots_per_bucket && o.pv == (uint32_t)pv && o.hk == p.hash_kind &&
-            o.threads == threads && o.lds == lds) {
+        if (o.hub == (uint32_t)hub && o.sw == sw && o.S == p.slots_per_bucket && o.pv == (uint32_t)pv &&
+            o.hk == p.hash_kind && o.threads == threads && o.lds == lds) {
             *per_cu = o.per_cu;
             return TC_OK;
         }
     int q = 0;
-    HIP_TRY(ctx, tc::count_kernel_info(hub, p.slots_per_bucket, pv, p.hash_kind, threads, lds, &q));
+    HIP_TRY(ctx, tc::count_kernel_info(hub, sw != 0, p.slots_per_bucket, pv, p.hash_kind, threads, lds, &q));
     if (q < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, lds);
-    ctx->occ.push_back({(uint32_t)hub, p.slots_per_bucket, (uint32_t)pv, p.hash_kind, threads, lds, q});
+    ctx->occ.push_back({(uint32_t)hub, sw, p.slots_per_bucket, (uint32_t)pv, p.hash_kind, threads, lds, q});
     *per_cu = q;
     return TC_OK;
 }
@@ -297,6 +309,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.wide = (g->m_in >= (1ull << 30)) || (p.flags & TC_F_WIDE_ADDR) ? 1u : 0u;
     a.shard = shard;
     a.shards = shards;
+    a.subwave = subwave_lanes(p.flags);
     const bool hub = needs_hub_launch(g);
     int per_cu = 0, per_cu_hub = 0;
     if (tc_status st = occupancy(ctx, p, pv, false, &per_cu)) return st;
@@ -312,11 +325,12 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
     if (hub) {
         a.table_words = launch_lds(ctx, p, true) / 4;
-        HIP_TRY(ctx, tc::count_launch(true, p.slots_per_bucket, pv, p.hash_kind, grid_hub, launch_threads(p, true),
+        HIP_TRY(ctx, tc::count_launch(true, false, p.slots_per_bucket, pv, p.hash_kind, grid_hub, launch_threads(p, true),
                                       launch_lds(ctx, p, true), a, s));
     }
     a.table_words = p.wg_lds_bytes / 4;
-    HIP_TRY(ctx, tc::count_launch(false, p.slots_per_bucket, pv, p.hash_kind, grid, launch_threads(p, false),
+    HIP_TRY(ctx, tc::count_launch(false, a.subwave != 0, p.slots_per_bucket, pv, p.hash_kind, grid,
+                                  launch_threads(p, false),
                                   p.wg_lds_bytes, a, s));
     if (rec) {
         HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));

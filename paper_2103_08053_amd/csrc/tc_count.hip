@@ -432,6 +432,40 @@ __device__ __forceinline__ unsigned long long probe_range(const Probe& pr, uint3
 }
 
 // Process vertex u with a group of `gsz` lanes (one wavefront, or the workgroup when WG).
+// Subwave intra-vertex assignment (the alternative to virtual combination that Section 4.2 compares
+// against): the wavefront is cut into groups of `sw` lanes (sw = 64: one list per wavefront, the
+// warp-centric baseline), global group gi of gn takes the out-neighbour records k = gi, gi + gn, ...,
+// and its lanes walk N+(v_k) with stride sw, each lane looking its element up along the bucket chain.
+// Instantiated in kernels of its own, so the default kernels carry none of it.
+template <int S, bool PV, int HK>
+__device__ __forceinline__ unsigned long long probe_subwave(const Probe& pr, uint32_t d, uint32_t gi0, uint32_t gn,
+                                                         uint32_t sw, int lane) {
+    const uint32_t sub = (uint32_t)lane / sw, in = (uint32_t)lane % sw, per_wave = 64u / sw;
+    uint32_t hits = 0;
+    for (uint32_t k0 = gi0 * per_wave; k0 < d; k0 += gn * per_wave) {  // uniform: the wavefront's groups
+        const uint32_t k = k0 + sub;
+        uint32_t len = 0, start = 0;
+        if (k < d) {
+            const uint32_t excl = k ? pr.P[k - 1].x : 0u;
+            const u32x2 rec = pr.P[k];
+            len = rec.x - excl;
+            start = rec.y + excl;
+        }
+        for (uint32_t t = in; t < len; t += sw) {
+            const uint32_t w = pr.col[(uint64_t)start + t];
+            uint32_t slot;
+            if (lookup_chain<S, HK>(pr.slots, w, pr.B, &slot)) {
+                ++hits;
+                if constexpr (PV) {
+                    atomicAdd(&pr.tslot[slot], 1u);
+                    atomicAdd(&pr.tally[k], 1u);
+                }
+            }
+        }
+    }
+    return wave_sum(hits);
+}
+
 struct NoMid {
     __device__ void operator()() const {}
 };
@@ -439,7 +473,7 @@ struct NoMid {
 // u's list is col[beg, beg + d) (uniform values).  With `pre` (one wavefront, d <= 64; uniform) the
 // lane's list element and that element's list (start, length) were loaded by the caller (xw, xo, xl).
 // `mid` runs after the table is built and before the probe (the caller issues its next loads there).
-template <int S, bool PV, int HK, bool WG, bool DEFER, typename Mid = NoMid>
+template <int S, bool PV, int HK, bool WG, bool DEFER, typename Mid = NoMid, bool SW = false>
 __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t beg, uint32_t d, uint32_t* tbl,
                                         uint64_t avail, int gl, int gsz, int gwave, int gnw, int lane,
                                         uint32_t* s_wsum, unsigned long long& acc, bool pre = false,
@@ -526,7 +560,9 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * r) / rn));
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * (r + 1)) / rn));
     const Probe pr{a.col, slots, P, tslot, tally, g.B};
-    const unsigned long long hits = probe_range<S, PV, HK, DEFER>(pr, d, lo, hi, lane, a.wide);
+    unsigned long long hits;
+    if constexpr (SW) hits = probe_subwave<S, PV, HK>(pr, d, r, rn, a.subwave, lane);
+    else hits = probe_range<S, PV, HK, DEFER>(pr, d, lo, hi, lane, a.wide);
     if (a.gid) {
         if (lane == 0 && hits) atomicAdd(&a.totals[a.gid[u]], hits);
     } else {
@@ -554,7 +590,7 @@ __device__ __forceinline__ bool in_shard(const CountArgs& a, uint32_t u) {
     return a.shards <= 1 || u % a.shards == a.shard;
 }
 
-template <int S, bool PV, int HK, bool DEFER>
+template <int S, bool PV, int HK, bool DEFER, bool SW = false>
 __device__ __forceinline__ void process_wg(const CountArgs& a, uint32_t u, uint32_t* tbl, uint64_t avail, int tid,
                                            int wave, int nw, int lane, uint32_t* s_wsum, unsigned long long& acc,
                                            uint32_t part = 0, uint32_t parts = 1) {
@@ -562,8 +598,8 @@ __device__ __forceinline__ void process_wg(const CountArgs& a, uint32_t u, uint3
     if (!in_shard(a, u)) return;
     const int64_t beg = a.off[u];
     const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(a.off[u + 1] - beg));
-    process<S, PV, HK, true, DEFER>(a, u, beg, d, tbl, avail, tid, blockDim.x, wave, nw, lane, s_wsum, acc, false,
-                                    0u, 0u, 0u, NoMid{}, part, parts);
+    process<S, PV, HK, true, DEFER, NoMid, SW>(a, u, beg, d, tbl, avail, tid, blockDim.x, wave, nw, lane, s_wsum, acc,
+                                               false, 0u, 0u, 0u, NoMid{}, part, parts);
 }
 
 // Tickets of a large-vertex bin of n vertices for `wgs` workgroups: when the bin has fewer vertices
@@ -627,8 +663,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);
 }
 
-// Everything else (bins 2 and 3): a persistent grid filling the GPU.
-template <int S, bool PV, int HK>
+// Everything else (bins 2 and 3): a persistent grid filling the GPU.  SW: subwave probe assignment.
+template <int S, bool PV, int HK, bool SW>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) tc_count_kernel(CountArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t s_wsum[kMaxWaves];
@@ -646,8 +682,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_wg) break;
-            process_wg<S, PV, HK, true>(a, a.items[n_before + j], lds, a.table_words, tid, wave, nw, lane, s_wsum,
-                                        acc);
+            process_wg<S, PV, HK, true, SW>(a, a.items[n_before + j], lds, a.table_words, tid, wave, nw, lane,
+                                            s_wsum, acc);
         }
     }
     // Wavefront bin: each wavefront owns a slice of the LDS and takes `chunk` vertices at a time.
@@ -721,8 +757,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                         }
                     };
                     if (in_shard(a, u))
-                        process<S, PV, HK, false, true>(a, u, beg, d, slice, a.slice_words, lane, 64, 0, 1, lane,
-                                                        nullptr, acc, d <= 64u, xw, xo, xl, mid);
+                        process<S, PV, HK, false, true, decltype(mid), SW>(a, u, beg, d, slice, a.slice_words, lane,
+                                                                           64, 0, 1, lane, nullptr, acc, d <= 64u, xw,
+                                                                           xo, xl, mid);
                     else
                         mid();
                     xw = nw;
@@ -738,36 +775,37 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
 
 typedef void (*KernelFn)(CountArgs);
 
-template <int S, bool HUB>
+template <int S, bool HUB, bool SW>
 KernelFn pick_hk(bool pv, uint32_t hk) {
     if constexpr (HUB) {
         if (pv) return hk ? tc_hub_kernel<S, true, 1> : tc_hub_kernel<S, true, 0>;
         return hk ? tc_hub_kernel<S, false, 1> : tc_hub_kernel<S, false, 0>;
     } else {
-        if (pv) return hk ? tc_count_kernel<S, true, 1> : tc_count_kernel<S, true, 0>;
-        return hk ? tc_count_kernel<S, false, 1> : tc_count_kernel<S, false, 0>;
+        if (pv) return hk ? tc_count_kernel<S, true, 1, SW> : tc_count_kernel<S, true, 0, SW>;
+        return hk ? tc_count_kernel<S, false, 1, SW> : tc_count_kernel<S, false, 0, SW>;
     }
 }
 
-template <bool HUB>
+template <bool HUB, bool SW>
 KernelFn pick(uint32_t S, bool pv, uint32_t hk) {
     switch (S) {
-        case 1: return pick_hk<1, HUB>(pv, hk);
-        case 2: return pick_hk<2, HUB>(pv, hk);
-        case 4: return pick_hk<4, HUB>(pv, hk);
+        case 1: return pick_hk<1, HUB, SW>(pv, hk);
+        case 2: return pick_hk<2, HUB, SW>(pv, hk);
+        case 4: return pick_hk<4, HUB, SW>(pv, hk);
         default: return nullptr;
     }
 }
 
-KernelFn pick_kernel(bool hub, uint32_t S, bool pv, uint32_t hk) {
-    return hub ? pick<true>(S, pv, hk) : pick<false>(S, pv, hk);
+KernelFn pick_kernel(bool hub, bool sw, uint32_t S, bool pv, uint32_t hk) {
+    if (hub) return pick<true, false>(S, pv, hk);
+    return sw ? pick<false, true>(S, pv, hk) : pick<false, false>(S, pv, hk);
 }
 
 }  // namespace
 
-hipError_t count_kernel_info(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads, uint32_t lds_bytes,
-                             int* blocks_per_cu) {
-    KernelFn f = pick_kernel(hub, S, pv, hash_kind);
+hipError_t count_kernel_info(bool hub, bool sw, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
+                             uint32_t lds_bytes, int* blocks_per_cu) {
+    KernelFn f = pick_kernel(hub, sw, S, pv, hash_kind);
     if (!f) return hipErrorInvalidValue;
     if (lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(f),
@@ -780,14 +818,14 @@ hipError_t count_kernel_info(bool hub, uint32_t S, bool pv, uint32_t hash_kind, 
 
 hipError_t count_kernel_static_lds(uint32_t* bytes) {
     hipFuncAttributes attr{};
-    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(pick_kernel(true, 4, true, 0)));
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(pick_kernel(true, false, 4, true, 0)));
     if (e == hipSuccess) *bytes = (uint32_t)attr.sharedSizeBytes;
     return e;
 }
 
-hipError_t count_launch(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
+hipError_t count_launch(bool hub, bool sw, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
                         uint32_t lds_bytes, const CountArgs& a, hipStream_t stream) {
-    KernelFn f = pick_kernel(hub, S, pv, hash_kind);
+    KernelFn f = pick_kernel(hub, sw, S, pv, hash_kind);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(grid), dim3(threads), lds_bytes, stream, a);
     return hipGetLastError();

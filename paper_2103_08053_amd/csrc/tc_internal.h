@@ -180,6 +180,7 @@ struct CountArgs {
     uint32_t table_words;            // LDS words of the workgroup table region (of this launch)
     uint32_t lrecip;                 // load_recip(load factor)
     uint32_t chunk;
+    uint32_t subwave;                // 0: virtual combination; 8/16/32/64: lanes per out-neighbour list
     uint32_t shard, shards;          // count only table owners u (rank) with u % shards == shard
     uint32_t wide;                   // col spans 4 GiB or more: 64-bit addressing in the probe
 };
@@ -226,11 +227,12 @@ hipError_t simple_capacity(uint32_t lds_bytes, uint32_t load_pct, uint32_t* max_
 hipError_t simple_launch(bool edge, bool build_only, uint32_t lds_bytes, int cu_count, const SimpleArgs& a,
                          hipStream_t stream);
 
-// tc_count.hip.  `hub` selects the large-vertex kernel (bins 0 and 1) instead of the main one.
-hipError_t count_kernel_info(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
+// tc_count.hip.  `hub` selects the large-vertex kernel (bins 0 and 1) instead of the main one; `sw` the
+// main kernel with subwave probe assignment.
+hipError_t count_kernel_info(bool hub, bool sw, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
                              uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t count_kernel_static_lds(uint32_t* bytes);
-hipError_t count_launch(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
+hipError_t count_launch(bool hub, bool sw, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
                         uint32_t lds_bytes, const CountArgs& a, hipStream_t stream);
 
 }  // namespace tc

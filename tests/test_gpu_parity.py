@@ -108,6 +108,8 @@ FORCED = [
     dict(flags=32),                             # every vertex in the large-LDS bin
     dict(flags=0x40), dict(flags=0x80),         # hash ids in in-degree / collective-degree order
     dict(flags=0x80 | 4, slots_per_bucket=1, load_factor_pct=100),
+    dict(flags=0x100), dict(flags=0x200), dict(flags=0x400), dict(flags=0x800),   # subwave / per-wave lists
+    dict(flags=0x100 | 4), dict(flags=0x200 | 32), dict(flags=0x400 | 2, slots_per_bucket=1, load_factor_pct=100),
     dict(wg_lds_bytes=4096, wg_waves=4),        # tiny LDS: most vertices spill to the global-table bin
     dict(slots_per_bucket=1), dict(slots_per_bucket=4),
     dict(load_factor_pct=100), dict(load_factor_pct=10),

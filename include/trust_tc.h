@@ -82,6 +82,9 @@ typedef struct tc_params {
 #define TC_F_SUBWAVE_16  0x200u  /* groups of 16 lanes */
 #define TC_F_SUBWAVE_32  0x400u  /* groups of 32 lanes */
 #define TC_F_WAVE_LIST   0x800u  /* one list per wavefront at a time (warp-centric) */
+#define TC_F_NO_PACK     0x1000u /* no packed bin: one wavefront per light vertex (default: vertices with
+                                    out-degree <= 32 and W(u) <= 1024 share wavefronts, 4 x 16 lanes when
+                                    out-degrees are <= 16, else 2 x 32 lanes) */
 
 /* Opaque handles. */
 typedef struct tc_context tc_context;
@@ -100,6 +103,8 @@ typedef struct tc_graph_info {
     uint32_t wg_cap;
     uint32_t n_big;       /* vertices in the large-LDS bin (one workgroup per CU with all of its LDS) */
     uint32_t big_cap;     /* out-degree limit of the large-LDS bin */
+    uint32_t n_packed;    /* light vertices (out-degree <= 32, W(u) <= 1024) packed 2-4 to a wavefront */
+    uint32_t reserved;
 } tc_graph_info;
 
 /* Fill *p with the default knobs (struct_size set). */

@@ -96,7 +96,7 @@ tc_status check_params(const tc_params* p) {
     if (p->hash_kind > 1) return TC_E_INVALID;
     if (p->light_chunk < 1 || p->light_chunk > 256) return TC_E_INVALID;
     if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SCATTER_CSR | TC_F_WIDE_ADDR |
-                     TC_F_FORCE_BIG | TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE | kIntraFlags))
+                     TC_F_FORCE_BIG | TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE | kIntraFlags | TC_F_NO_PACK))
         return TC_E_INVALID;
     if (__builtin_popcount(p->flags & kIntraFlags) > 1) return TC_E_INVALID;
     if ((p->flags & TC_F_ORDER_INDEGREE) && (p->flags & TC_F_ORDER_COLLECTIVE)) return TC_E_INVALID;
@@ -106,6 +106,9 @@ tc_status check_params(const tc_params* p) {
 uint32_t slice_words(const tc_params& p) {
     return (p.wg_lds_bytes / 4 / p.wg_waves) & ~3u;
 }
+
+// LDS words of a packed light vertex's table: a quarter of a wavefront slice.
+uint32_t pack_region(const tc_params& p) { return (slice_words(p) / 4) & ~3u; }
 
 tc::BinCaps bin_caps(const tc_context* ctx, const tc_params& p) {
     tc::BinCaps c{};
@@ -118,6 +121,14 @@ tc::BinCaps bin_caps(const tc_context* ctx, const tc_params& p) {
     c.force_wg = (p.flags & TC_F_FORCE_WG) != 0;
     c.force_hub = (p.flags & TC_F_FORCE_HUB) != 0;
     c.force_big = (p.flags & TC_F_FORCE_BIG) != 0;
+    // Packed bin: out-degree up to 32 whose minimal table fits a quarter slice (subwave modes and
+    // TC_F_NO_PACK keep one wavefront per vertex).
+    c.pack_cap = 0;
+    if (!(p.flags & (TC_F_NO_PACK | kIntraFlags))) {
+        c.pack_cap = std::min<uint32_t>({tc::kPackMaxD, c.wave_cap,
+                                         tc::capacity(pack_region(p), p.slots_per_bucket, p.load_factor_pct, true)});
+        if (c.pack_cap < 2) c.pack_cap = 0;
+    }
     c.lpt = (p.flags & TC_F_NO_LPT) == 0;
     c.scatter_csr = (p.flags & TC_F_SCATTER_CSR) != 0;
     c.order = (p.flags & TC_F_ORDER_INDEGREE) ? 1u : (p.flags & TC_F_ORDER_COLLECTIVE) ? 2u : 0u;
@@ -310,6 +321,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.shard = shard;
     a.shards = shards;
     a.subwave = subwave_lanes(p.flags);
+    a.pack_region = pack_region(p);
     const bool hub = needs_hub_launch(g);
     int per_cu = 0, per_cu_hub = 0;
     if (tc_status st = occupancy(ctx, p, pv, false, &per_cu)) return st;
@@ -569,6 +581,7 @@ tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out)
     out->n_big = m.bins[1];
     out->n_wg = m.bins[2];
     out->n_wave = m.bins[3];
+    out->n_packed = m.bins[4];
     if (m.err & 1u) return TC_E_RANGE;
     return TC_OK;
 }
@@ -652,6 +665,7 @@ tc_status tc_graph_collisions(tc_context* ctx, const tc_graph* g, int per_vertex
     a.avail[1] = ctx->big_lds_bytes / 4;
     a.avail[2] = p.wg_lds_bytes / 4;
     a.avail[3] = slice_words(p);
+    a.avail[4] = pack_region(p);
     a.S = p.slots_per_bucket;
     a.lrecip = tc::load_recip(p.load_factor_pct);
     a.hash_kind = p.hash_kind;

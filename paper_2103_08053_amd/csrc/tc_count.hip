@@ -584,6 +584,139 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
     group_sync<WG>();  // the table memory is reused by the next vertex
 }
 
+// Inclusive prefix sum within groups of G lanes (16 or 32) by DPP row moves.
+template <int G>
+__device__ __forceinline__ uint32_t group_incl_scan(uint32_t v) {
+    v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+    if constexpr (G == 32) v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    return v;
+}
+
+// Several light vertices in one wavefront: group g = lane / G (64 / G groups) takes the vertex
+// (ug, list at col[bg, bg + dg)) when `has`, with its table in the g-th part of the wavefront's LDS
+// slice (`region` words each), and walks its own flattened 2-hop index space G lanes at a time
+// (loads of kUnroll steps issued before they are looked up; lookups walk their bucket chain lane by
+// lane, which the lightly loaded tables of small vertices keep short).  The per-vertex fixed work
+// (clears, build, records, reductions, flushes) is shared by the groups instead of paid per vertex.
+template <int S, bool PV, int HK, int G>
+__device__ __forceinline__ void process_packed(const CountArgs& a, uint32_t ug, uint32_t bg, uint32_t dg, bool has,
+                                               uint32_t* slice, uint32_t region, int lane,
+                                               unsigned long long& acc) {
+    const uint32_t g = (uint32_t)lane / G, gl = (uint32_t)lane % G;
+    const uint32_t d = has ? dg : 0u;
+    const Geometry geo = geometry_fit(d, S, a.lrecip, PV, region);
+    uint32_t* base = slice + g * (64u / G == 4 ? region : 2u * region);
+    uint32_t* slots = base;
+    uint32_t* len = base + geo.o_len;
+    u32x2* P = reinterpret_cast<u32x2*>(base + geo.o_P);
+    uint32_t* tslot = base + geo.o_tslot;
+    uint32_t* tally = base + geo.o_tally;
+    for (uint32_t x = gl; x < geo.B * S; x += G) slots[x] = kEmpty;
+    for (uint32_t x = gl; x < geo.B; x += G) len[x] = 0;
+    if constexpr (PV) {
+        for (uint32_t x = gl; x < geo.B * S; x += G) tslot[x] = 0;
+        if (gl < d) tally[gl] = 0;
+    }
+    wave_sync();
+    // Build (one element per lane: d <= G) and the 2-hop records.
+    uint32_t lv = 0, o0 = 0;
+    if (gl < d) {
+        const uint32_t w = a.col[(uint64_t)bg + gl];
+        uint32_t b = hash_of<HK>(w, geo.B), pos;
+        for (;;) {
+            pos = atomicAdd(&len[b], 1u);
+            if (pos < (uint32_t)S) break;
+            b = (b + 1) & geo.mask;
+        }
+        slots[b * S + pos] = w;
+        o0 = (uint32_t)a.off[w];
+        lv = (uint32_t)a.off[w + 1] - o0;
+    }
+    const uint32_t incl = group_incl_scan<G>(lv);
+    const uint32_t W = (uint32_t)__shfl((int)incl, (int)(g * G + G - 1), 64);
+    if (gl < d) P[gl] = u32x2{incl, o0 - (incl - lv)};
+    wave_sync();
+    // Probe: step c covers indices c * G + gl of the group's range [0, W).
+    uint32_t steps = (W + G - 1) / G, m = steps;
+    for (int o = G; o < 64; o <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_xor((int)m, o, 64);
+        m = t > m ? t : m;
+    }
+    const uint32_t maxsteps = __builtin_amdgcn_readfirstlane(m);
+    uint32_t k = 0, cur = 0, end = 0, hits = 0;
+    if (gl < W) {
+        uint32_t l = 0, r = d - 1;
+        while (l < r) {
+            const uint32_t mid = (l + r) >> 1;
+            if (P[mid].x > gl) r = mid; else l = mid + 1;
+        }
+        k = l;
+        const u32x2 rec = P[k];
+        cur = rec.y + gl;
+        end = rec.y + rec.x;
+    }
+    for (uint32_t c0 = 0; c0 < maxsteps; c0 += kUnroll) {
+        uint32_t w[kUnroll], kk[kUnroll];
+        bool act[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const uint32_t ii = (c0 + j) * G + gl;
+            act[j] = ii < W;
+            w[j] = 0;
+            kk[j] = k;
+            if (act[j]) {
+                while (cur >= end) {
+                    ++k;
+                    const u32x2 rec = P[k];
+                    cur = rec.y + ii;
+                    end = rec.y + rec.x;
+                }
+                w[j] = a.col[cur];
+                kk[j] = k;
+                cur += G;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            uint32_t slot;
+            if (act[j] && lookup_chain<S, HK>(slots, w[j], geo.B, &slot)) {
+                ++hits;
+                if constexpr (PV) {
+                    atomicAdd(&tslot[slot], 1u);
+                    atomicAdd(&tally[kk[j]], 1u);
+                }
+            }
+        }
+    }
+    // Per-group totals (lane G - 1 of each group holds its group's sum).
+    const uint32_t hs = group_incl_scan<G>(hits);
+    const bool last = gl == G - 1;
+    if (a.gid) {
+        if (last && has && hs) atomicAdd(&a.totals[a.gid[ug]], (unsigned long long)hs);
+    } else {
+        uint32_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < 64 / G; ++q) sum += (uint32_t)__builtin_amdgcn_readlane((int)hs, q * G + G - 1);
+        acc += sum;
+    }
+    if constexpr (PV) {
+        if (last && has && hs) atomicAdd(&a.tv[ug], (unsigned long long)hs);
+        wave_sync();
+        if (gl < d) {
+            const uint32_t t = tally[gl];
+            if (t) atomicAdd(&a.tv[a.col[(uint64_t)bg + gl]], (unsigned long long)t);
+        }
+        for (uint32_t x = gl; x < geo.B * S; x += G) {
+            const uint32_t t = tslot[x];
+            if (t) atomicAdd(&a.tv[slots[x]], (unsigned long long)t);
+        }
+    }
+    wave_sync();  // the slice is reused by the next vertex
+}
+
 // Workgroup-owned vertex: its list from the offsets, then process().
 // Whether this launch counts the triangles owned by u (workload partitioning: u % shards == shard).
 __device__ __forceinline__ bool in_shard(const CountArgs& a, uint32_t u) {
@@ -673,6 +806,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     unsigned long long acc = 0;
     const uint32_t n_before = a.meta->bins[0] + a.meta->bins[1], n_wg = a.meta->bins[2], n_wave = a.meta->bins[3];
+    const uint32_t n_pack = a.meta->bins[4];
 
     // Workgroup bin: the table fills the workgroup's LDS.
     if (n_wg) {
@@ -686,21 +820,20 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                                             s_wsum, acc);
         }
     }
-    // Wavefront bin: each wavefront owns a slice of the LDS and takes `chunk` vertices at a time.
-    // Chunk c belongs to sub-queue c % kWaveQueues (interleaved, so every sub-queue keeps the
+    // Wavefront bins: each wavefront owns a slice of the LDS and takes `per_fetch` vertices at a time.
+    // Chunk c of a bin belongs to sub-queue c % kWaveQueues (interleaved, so every sub-queue keeps the
     // largest-work-first order); each sub-queue counter has a cache line of its own, which spreads
     // the fetch atomics of a launch with millions of light vertices over kWaveQueues addresses.  A
     // wavefront starts on sub-queue blockIdx % kWaveQueues (one per XCD with round-robin dispatch),
     // moves on when its sub-queue is drained, and requests its next chunk before working on the
-    // current one.
-    {
-        uint32_t* slice = lds + (size_t)wave * a.slice_words;
-        const uint32_t base = n_before + n_wg;
-        const uint32_t nchunks = (n_wave + a.chunk - 1) / a.chunk;
+    // current one.  `work(j0, j1)` processes items [j0, j1) of the bin.
+    uint32_t* slice = lds + (size_t)wave * a.slice_words;
+    auto drain = [&](uint32_t n_bin, uint32_t per_fetch, uint32_t head0, auto&& work) {
+        const uint32_t nchunks = (n_bin + per_fetch - 1) / per_fetch;
         uint32_t q = blockIdx.x % kWaveQueues, drained = 0;
         auto request = [&]() -> uint32_t {
             uint32_t c = 0;
-            if (lane == 0) c = atomicAdd(&a.heads[(3 + q) * kHeadStride], 1u);
+            if (lane == 0) c = atomicAdd(&a.heads[(head0 + q) * kHeadStride], 1u);
             return c;
         };
         // Chunk index from a sub-queue ticket, moving on through drained sub-queues (nchunks: all done).
@@ -716,30 +849,39 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         uint32_t cur = settle(request());
         while (cur < nchunks) {
             const uint32_t ticket = request();  // next chunk, settled after this one
-            const uint32_t j0 = cur * a.chunk;
-            const uint32_t j1 = (j0 + a.chunk < n_wave) ? j0 + a.chunk : n_wave;
+            const uint32_t j0 = cur * per_fetch;
+            work(j0, (j0 + per_fetch < n_bin) ? j0 + per_fetch : n_bin);
+            cur = settle(ticket);
+        }
+    };
+    // Bin 3: one vertex per wavefront.
+    {
+        const uint32_t wbase = n_before + n_wg;
+        drain(n_wave, a.chunk, 3u, [&](uint32_t j0, uint32_t j1) {
             // The vertices of a fetch and their list bounds are loaded by the wavefront at once
             // (lane i holds the i-th), so each vertex starts without two dependent loads.
             for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
                 const uint32_t cnt = (j1 - b0 < 64u) ? j1 - b0 : 64u;
                 uint32_t vu = 0, vb = 0, vd = 0;  // offsets stay below 2^31 (m < 2^31)
                 if ((uint32_t)lane < cnt) {
-                    vu = a.items[base + b0 + lane];
+                    vu = a.items[wbase + b0 + lane];
                     vb = (uint32_t)a.off[vu];
                     vd = (uint32_t)a.off[vu + 1] - vb;
                 }
                 // Two-stage prefetch for lists of at most 64: the next vertex's list is loaded while
                 // this one's table is built, and its elements' list bounds while this one is probed.
                 uint32_t xw = 0, xo = 0, xl = 0;
-                {
-                    const int64_t beg0 = (int64_t)__builtin_amdgcn_readlane(vb, 0);
-                    const uint32_t d0 = __builtin_amdgcn_readlane(vd, 0);
+                auto prime = [&](uint32_t i0) {  // vertex i0's list element and its bounds, loaded now
+                    const int64_t beg0 = (int64_t)__builtin_amdgcn_readlane(vb, i0);
+                    const uint32_t d0 = __builtin_amdgcn_readlane(vd, i0);
+                    xw = xo = xl = 0;
                     if (d0 <= 64u && (uint32_t)lane < d0) {
                         xw = a.col[beg0 + lane];
                         xo = (uint32_t)a.off[xw];
                         xl = (uint32_t)a.off[xw + 1] - xo;
                     }
-                }
+                };
+                prime(0);
                 for (uint32_t i = 0; i < cnt; ++i) {
                     const uint32_t u = __builtin_amdgcn_readlane(vu, i);
                     const int64_t beg = (int64_t)__builtin_amdgcn_readlane(vb, i);
@@ -767,8 +909,41 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                     xl = nl;
                 }
             }
-            cur = settle(ticket);
-        }
+        });
+    }
+    // Bin 4: light vertices (out-degree <= 32, small collective degree) packed several to a
+    // wavefront: 4 x 16 lanes when the next 3 or 4 have out-degree <= 16, else 2 x 32 lanes.
+    if constexpr (!SW) {
+        const uint32_t pbase = n_before + n_wg + n_wave;
+        drain(n_pack, 4u * a.chunk, 3u + kWaveQueues, [&](uint32_t j0, uint32_t j1) {
+            for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
+                const uint32_t cnt = (j1 - b0 < 64u) ? j1 - b0 : 64u;
+                uint32_t vu = 0, vb = 0, vd = 0;
+                if ((uint32_t)lane < cnt) {
+                    vu = a.items[pbase + b0 + lane];
+                    vb = (uint32_t)a.off[vu];
+                    vd = (uint32_t)a.off[vu + 1] - vb;
+                }
+                for (uint32_t i = 0; i < cnt;) {
+                    uint32_t n16 = 0;
+                    while (n16 < 4 && i + n16 < cnt && __builtin_amdgcn_readlane(vd, i + n16) <= 16u) ++n16;
+                    const bool use16 = n16 >= 3;
+                    const uint32_t np = use16 ? n16 : (i + 1 < cnt ? 2u : 1u);
+                    const uint32_t gsz = use16 ? 16u : 32u;
+                    const uint32_t gi = (uint32_t)lane / gsz;
+                    const int src = (int)(i + (gi < np ? gi : np - 1));
+                    const uint32_t ug = (uint32_t)__shfl((int)vu, src, 64);
+                    const uint32_t bg = (uint32_t)__shfl((int)vb, src, 64);
+                    const uint32_t dg = (uint32_t)__shfl((int)vd, src, 64);
+                    const bool has = gi < np && in_shard(a, ug);
+                    if (use16)
+                        process_packed<S, PV, HK, 16>(a, ug, bg, dg, has, slice, a.pack_region, lane, acc);
+                    else
+                        process_packed<S, PV, HK, 32>(a, ug, bg, dg, has, slice, a.pack_region, lane, acc);
+                    i += np;
+                }
+            }
+        });
     }
     add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);
 }

@@ -1,6 +1,6 @@
 // Collision statistics of the hash tables the count kernels build (paper Section 4.1, Equation 2).
 //
-// For every scheduled vertex u (bins 0-3) this recomputes the bucket count B of u's table exactly
+// For every scheduled vertex u (bins 0-4) this recomputes the bucket count B of u's table exactly
 // as the count kernels size it (same bin capacity, same geometry) and histograms the home bucket
 // hash(w) of every w in N+(u).  The maximum bucket load is the "max collision" of u; the estimate of
 // Equation 2 weighs it with the collective degree W(u) = sum of d+(v) over v in N+(u):
@@ -20,11 +20,12 @@ __global__ void __launch_bounds__(kDiagThreads) k_collisions(DiagArgs a) {
     __shared__ unsigned long long s_w;
     __shared__ uint32_t s_max;
     const uint32_t nb0 = a.meta->bins[0], nb1 = a.meta->bins[1], nb2 = a.meta->bins[2], nb3 = a.meta->bins[3];
-    const uint32_t total = nb0 + nb1 + nb2 + nb3;
+    const uint32_t total = nb0 + nb1 + nb2 + nb3 + a.meta->bins[4];
     unsigned long long phi = 0, summax = 0, tables = 0;
     uint32_t maxall = 0;
     for (uint32_t j = blockIdx.x; j < total; j += gridDim.x) {
-        const uint32_t bin = j < nb0 ? 0u : j < nb0 + nb1 ? 1u : j < nb0 + nb1 + nb2 ? 2u : 3u;
+        const uint32_t bin = j < nb0 ? 0u : j < nb0 + nb1 ? 1u : j < nb0 + nb1 + nb2 ? 2u
+                           : j < nb0 + nb1 + nb2 + nb3 ? 3u : 4u;
         const uint32_t u = a.items[j];
         const int64_t beg = a.off[u];
         const uint32_t d = (uint32_t)(a.off[u + 1] - beg);

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(kSimpleThreads) k_simple(SimpleArgs a) {
     __shared__ uint32_t s_item;
     __shared__ unsigned long long s_acc[kSimpleThreads / 64];
     const uint32_t tid = threadIdx.x;
-    const uint32_t n_tab = a.meta->bins[0] + a.meta->bins[1] + a.meta->bins[2] + a.meta->bins[3];
+    const uint32_t n_tab = a.meta->bins[0] + a.meta->bins[1] + a.meta->bins[2] + a.meta->bins[3] + a.meta->bins[4];
     unsigned long long acc = 0;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(a.head, kSimpleChunk);

@@ -12,11 +12,14 @@ namespace tc {
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash slot; never a valid id (ids < n <= 2^32 - 1)
 constexpr uint32_t kMaxWaves = 16;
 constexpr uint32_t kHubWgs = 128;        // workgroups that take global-memory-table vertices
-// Queue heads of the count launches: bins 0-2 and kWaveQueues sub-queues of the wavefront bin, each
+// Queue heads of the count launches: bins 0-2 and kWaveQueues sub-queues of each wavefront bin, each
 // counter in a 128-byte line of its own (kHeadStride words apart).
 constexpr uint32_t kWaveQueues = 8;
 constexpr uint32_t kHeadStride = 32;
-constexpr uint32_t kHeadWords = (3 + kWaveQueues) * kHeadStride;
+constexpr uint32_t kHeadWords = (3 + 2 * kWaveQueues) * kHeadStride;
+// Packed bin: out-degree at most 32 and collective degree W(u) at most this (a few steps of 16 lanes).
+constexpr uint32_t kPackMaxWork = 512;
+constexpr uint32_t kPackMaxD = 32;
 
 // Device-resident summary of a built graph (first 256 bytes of its storage).
 struct GraphMeta {
@@ -26,9 +29,10 @@ struct GraphMeta {
     unsigned int max_dplus;
     unsigned int err;               // bit 0: some input id >= n
     // vertex counts: global-memory tables, large LDS tables (one workgroup per CU), workgroup LDS
-    // tables, wavefront LDS slices, skipped (d+ < 2 or no 2-hop work)
-    unsigned int bins[5];
-    unsigned int pad[52];
+    // tables, wavefront LDS slices, light vertices packed several per wavefront, skipped (d+ < 2 or
+    // no 2-hop work)
+    unsigned int bins[6];
+    unsigned int pad[51];
 };
 static_assert(sizeof(GraphMeta) == 256, "meta is one 256-byte block");
 
@@ -145,6 +149,7 @@ struct BuildTemp {
 
 struct BinCaps {
     uint32_t wave_cap, wg_cap, big_cap;
+    uint32_t pack_cap;  // out-degree limit of the packed bin (0: no packing)
     bool force_wg, force_hub, force_big, lpt, scatter_csr;
     uint32_t order;  // hash-id order: 0 (degree, id) rank, 1 in-degree, 2 collective degree
 };
@@ -180,6 +185,7 @@ struct CountArgs {
     uint32_t table_words;            // LDS words of the workgroup table region (of this launch)
     uint32_t lrecip;                 // load_recip(load factor)
     uint32_t chunk;
+    uint32_t pack_region;            // LDS words of a packed vertex's table (a quarter of a wavefront slice)
     uint32_t subwave;                // 0: virtual combination; 8/16/32/64: lanes per out-neighbour list
     uint32_t shard, shards;          // count only table owners u (rank) with u % shards == shard
     uint32_t wide;                   // col spans 4 GiB or more: 64-bit addressing in the probe
@@ -195,14 +201,14 @@ hipError_t gather_per_vertex(const unsigned long long* tv_rank, const uint32_t* 
                              unsigned long long* out, hipStream_t stream);
 
 // tc_diag.hip: per-table collision statistics of a built graph (the cost model of Equation 2) for
-// the tables the count kernels build; avail[bin] = table words of bins 0-3.  stats = {phi,
+// the tables the count kernels build; avail[bin] = table words of bins 0-4.  stats = {phi,
 // sum of max collisions, tables, largest collision} (zeroed here).
 struct DiagArgs {
     const GraphMeta* meta;
     const int64_t* off;
     const uint32_t* col;
     const uint32_t* items;
-    uint32_t avail[4];
+    uint32_t avail[5];
     uint32_t S, lrecip, hash_kind, pv;
     unsigned long long* stats;
 };

@@ -246,26 +246,29 @@ __global__ void k_csr_runs(const unsigned long long* __restrict__ okeys, uint32_
 // inclusive scan of d+(col[e]) over the edges), bin, and the sort key
 // (bin << 40 | reversed work).  Bins: 0 global-memory table (too large for
 // any LDS table), 1 large LDS table (whole LDS of a workgroup, one per CU),
-// 2 workgroup LDS table, 3 wavefront LDS slice, 4 skipped.
+// 2 workgroup LDS table, 3 wavefront LDS slice, 4 light vertices packed
+// several to a wavefront, 5 skipped.
 __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long long* __restrict__ wscan, uint32_t n,
                            BinCaps caps, GraphMeta* meta, unsigned long long* __restrict__ skey) {
     __shared__ unsigned long long s_w;
-    __shared__ unsigned int s_max, s_bins[5];
-    if (threadIdx.x == 0) { s_w = 0; s_max = 0; s_bins[0] = s_bins[1] = s_bins[2] = s_bins[3] = s_bins[4] = 0; }
+    __shared__ unsigned int s_max, s_bins[6];
+    if (threadIdx.x < 6) s_bins[threadIdx.x] = 0;
+    if (threadIdx.x == 0) { s_w = 0; s_max = 0; }
     __syncthreads();
     const unsigned long long kWorkMax = (1ull << 40) - 1;
     // Per-thread partials, reduced across the wave, then one LDS atomic per wave.
     unsigned long long wsum = 0;
-    uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0;
+    uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0, nb5 = 0;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         const int64_t b = off[r], e = off[r + 1];
         const uint32_t d = (uint32_t)(e - b);
         const unsigned long long w = d ? wscan[e - 1] - (b ? wscan[b - 1] : 0ull) : 0ull;
         uint32_t bin;
-        if (d < 2 || w == 0) bin = 4;
+        if (d < 2 || w == 0) bin = 5;
         else if (caps.force_hub || d > caps.big_cap) bin = 0;
         else if (caps.force_big || d > caps.wg_cap) bin = 1;
         else if (caps.force_wg || d > caps.wave_cap) bin = 2;
+        else if (d <= caps.pack_cap && w <= kPackMaxWork) bin = 4;
         else bin = 3;
         const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
         skey[r] = ((unsigned long long)bin << 40) | (caps.lpt ? (kWorkMax - wk) : 0ull);
@@ -276,6 +279,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         nb2 += bin == 2;
         nb3 += bin == 3;
         nb4 += bin == 4;
+        nb5 += bin == 5;
     }
     for (int o = 32; o > 0; o >>= 1) {
         wsum += __shfl_xor(wsum, o);
@@ -286,6 +290,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         nb2 += __shfl_xor(nb2, o);
         nb3 += __shfl_xor(nb3, o);
         nb4 += __shfl_xor(nb4, o);
+        nb5 += __shfl_xor(nb5, o);
     }
     if ((threadIdx.x & 63) == 0) {
         atomicAdd(&s_w, wsum);
@@ -295,12 +300,13 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         atomicAdd(&s_bins[2], nb2);
         atomicAdd(&s_bins[3], nb3);
         atomicAdd(&s_bins[4], nb4);
+        atomicAdd(&s_bins[5], nb5);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(&meta->wplus, s_w);
         atomicMax(&meta->max_dplus, s_max);
-        for (int i = 0; i < 5; ++i) atomicAdd(&meta->bins[i], s_bins[i]);
+        for (int i = 0; i < 6; ++i) atomicAdd(&meta->bins[i], s_bins[i]);
     }
 }
 

@@ -52,7 +52,8 @@ class _GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("m", ctypes.c_uint64), ("wedges_plus", ctypes.c_uint64),
                 ("max_dplus", ctypes.c_uint32), ("n_hub", ctypes.c_uint32), ("n_wg", ctypes.c_uint32),
                 ("n_wave", ctypes.c_uint32), ("wave_cap", ctypes.c_uint32), ("wg_cap", ctypes.c_uint32),
-                ("n_big", ctypes.c_uint32), ("big_cap", ctypes.c_uint32)]
+                ("n_big", ctypes.c_uint32), ("big_cap", ctypes.c_uint32), ("n_packed", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 @dataclass
@@ -93,6 +94,8 @@ class GraphInfo:
     wg_cap: int
     n_big: int = 0
     big_cap: int = 0
+    n_packed: int = 0
+    reserved: int = 0
 
 
 _lib = None

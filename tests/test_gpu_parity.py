@@ -322,15 +322,16 @@ def test_shard_arguments_checked(ctx, torch):
 # ----------------------------------------------------------------------------- collision statistics
 
 def test_collision_stats_complete_graph(ctx, torch):
-    """K_100: N+(u) is a run of consecutive ranks and (default knobs, d+ < 100) every table has
-    B >= d+ buckets, so with the low-bits hash no two out-neighbours share a home bucket: max
-    collision 1 everywhere and phi (Equation 2) = W+."""
+    """K_100: N+(u) is a run of consecutive ranks and (default knobs without the packed bin's
+    quarter-slice tables, d+ < 100) every table has B >= d+ buckets, so with the low-bits hash no
+    two out-neighbours share a home bucket: max collision 1 everywhere and phi (Equation 2) = W+."""
+    from paper_2103_08053_amd import Context, Params
     g = gg.complete(100)
-    graph = ctx.build(g.src, g.dst, g.n)
+    graph = Context(0, Params(flags=0x1000)).build(g.src, g.dst, g.n)
     info = graph.info()
     for pv in (True, False):
         st = graph.collisions(per_vertex=pv)
-        assert st["tables"] == g.n - 2 == info.n_wave + info.n_wg + info.n_big + info.n_hub
+        assert st["tables"] == g.n - 2 == info.n_wave + info.n_wg + info.n_big + info.n_hub + info.n_packed
         assert st["max_collision"] == 1 and st["sum_max_collision"] == st["tables"]
         assert st["phi"] == info.wedges_plus
 
@@ -345,7 +346,7 @@ def test_collision_stats_bounds(torch):
     a, b = lo.collisions(), hi.collisions()
     for st, gr in ((a, lo), (b, hi)):
         info = gr.info()
-        assert st["tables"] == info.n_wave + info.n_wg + info.n_big + info.n_hub
+        assert st["tables"] == info.n_wave + info.n_wg + info.n_big + info.n_hub + info.n_packed
         assert st["sum_max_collision"] >= st["tables"] and st["max_collision"] >= 1
         assert st["phi"] >= st["sum_max_collision"]
     assert b["sum_max_collision"] >= a["sum_max_collision"]
@@ -384,3 +385,26 @@ def test_plain_designs_reject_what_they_cannot_hold(torch):
     b = Batch(c, [(5, gg.complete(5).src, gg.complete(5).dst)] * 2)
     with pytest.raises(TCError):
         b.count_simple()
+
+
+# ----------------------------------------------------------------------------- packed light vertices
+
+def test_packed_light_vertices_match_unpacked(torch):
+    """Runs of light vertices share a wavefront (4 x 16 or 2 x 32 lanes); the counts equal the
+    one-vertex-per-wavefront path and the oracle, per vertex too, also in batches and shards."""
+    from paper_2103_08053_amd import Batch, Context, Params
+    gs = [gg.dirty(gg.erdos_renyi(5000, 40000, seed=3), seed=4), gg.erdos_renyi(20000, 320000, seed=5),
+          gg.barabasi_albert(4000, 6, seed=6), gg.complete(20), gg.cycle(50), gg.torus3d(7)]
+    for kw in (dict(), dict(flags=0x1000), dict(load_factor_pct=10), dict(slots_per_bucket=1, load_factor_pct=100),
+               dict(wg_lds_bytes=8192), dict(hash_kind=1), dict(flags=0x40)):
+        c = Context(0, Params(**kw))
+        if not kw:
+            info = c.build(gs[1].src, gs[1].dst, gs[1].n).info()
+            assert info.n_packed > 0
+        for g in gs:
+            assert_parity(c, g)
+        b = Batch(c, [(g.n, g.src, g.dst) for g in gs])
+        assert b.count()[0] == [oracle.count(g.n, g.src, g.dst).total for g in gs], kw
+    g = gs[1]
+    graph = Context(0).build(g.src, g.dst, g.n)
+    assert sum(graph.count(shard=(s, 3))[0] for s in range(3)) == oracle.count(g.n, g.src, g.dst).total

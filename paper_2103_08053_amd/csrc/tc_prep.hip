@@ -113,8 +113,17 @@ __global__ void k_canon_batch(const uint32_t* __restrict__ src, const uint32_t* 
     if (blockIdx.x == 0 && threadIdx.x == 0 &&
         (voff[0] != 0 || eoff[0] != 0 || voff[k] != n || eoff[k] != m_in))
         bad = 1;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < m_in; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t g = owner(eoff, k, i);
+    // The graph of sample i: one binary search per block and step (its first sample), then each
+    // thread moves forward over the few graphs a run of blockDim samples can span.
+    __shared__ uint32_t s_g;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < m_in; base += (uint64_t)gridDim.x * blockDim.x) {
+        if (threadIdx.x == 0) s_g = owner(eoff, k, base);
+        __syncthreads();
+        const uint64_t i = base + threadIdx.x;
+        uint32_t g = s_g;
+        __syncthreads();
+        if (i >= m_in) continue;
+        while (g + 1 < k && eoff[g + 1] <= i) ++g;
         const unsigned long long v0 = voff[g], ng = voff[g + 1] - v0;
         const unsigned long long a = (unsigned long long)src[i] + v0, b = (unsigned long long)dst[i] + v0;
         unsigned long long key;
@@ -244,7 +253,7 @@ __global__ void k_csr_runs(const unsigned long long* __restrict__ okeys, uint32_
 
 // One thread per vertex: d+, W(u) = sum of d+(v) over v in N+(u) (from the
 // inclusive scan of d+(col[e]) over the edges), bin, and the sort key
-// (bin << 40 | reversed work).  Bins: 0 global-memory table (too large for
+// (bin << 24 | reversed work, clamped to 24 bits).  Bins: 0 global-memory table (too large for
 // any LDS table), 1 large LDS table (whole LDS of a workgroup, one per CU),
 // 2 workgroup LDS table, 3 wavefront LDS slice, 4 light vertices packed
 // several to a wavefront, 5 skipped.
@@ -255,7 +264,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
     if (threadIdx.x < 6) s_bins[threadIdx.x] = 0;
     if (threadIdx.x == 0) { s_w = 0; s_max = 0; }
     __syncthreads();
-    const unsigned long long kWorkMax = (1ull << 40) - 1;
+    const unsigned long long kWorkMax = (1ull << 24) - 1;  // larger work ties: LPT order is a heuristic
     // Per-thread partials, reduced across the wave, then one LDS atomic per wave.
     unsigned long long wsum = 0;
     uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0, nb5 = 0;
@@ -271,7 +280,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         else if (d <= caps.pack_cap && w <= kPackMaxWork) bin = 4;
         else bin = 3;
         const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
-        skey[r] = ((unsigned long long)bin << 40) | (caps.lpt ? (kWorkMax - wk) : 0ull);
+        skey[r] = ((unsigned long long)bin << 24) | (caps.lpt ? (kWorkMax - wk) : 0ull);
         wsum += w;
         dmax = d > dmax ? d : dmax;
         nb0 += bin == 0;
@@ -622,7 +631,7 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     TC_TRY(hipGetLastError());
     tmp = t.sort_tmp_bytes;
     TC_TRY(rocprim::radix_sort_pairs(t.sort_tmp, tmp, t.skey_a, t.skey_b, rocprim::counting_iterator<uint32_t>(0),
-                                     g.items, (size_t)n, 0, 43, stream));
+                                     g.items, (size_t)n, 0, 27, stream));
     return hipSuccess;
 }
 

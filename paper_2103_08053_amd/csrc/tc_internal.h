@@ -32,7 +32,8 @@ struct GraphMeta {
     // tables, wavefront LDS slices, light vertices packed several per wavefront, skipped (d+ < 2 or
     // no 2-hop work)
     unsigned int bins[6];
-    unsigned int pad[51];
+    unsigned int wave_cands, pack_cands;  // census before binning: wavefront-size tables, and packable ones
+    unsigned int pad[49];
 };
 static_assert(sizeof(GraphMeta) == 256, "meta is one 256-byte block");
 

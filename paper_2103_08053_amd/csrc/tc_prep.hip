@@ -251,6 +251,30 @@ __global__ void k_csr_runs(const unsigned long long* __restrict__ okeys, uint32_
     }
 }
 
+// Census for the packed bin: vertices that would get a wavefront-size table, and how many of them
+// are light enough to pack (out-degree <= pack_cap, W(u) <= kPackMaxWork).  Packing pays when light
+// vertices dominate (their per-vertex fixed work is what it shares); the schedule packs only then.
+__global__ void k_pack_census(const int64_t* __restrict__ off, const unsigned long long* __restrict__ wscan,
+                              uint32_t n, BinCaps caps, GraphMeta* meta) {
+    uint32_t wc = 0, pc = 0;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int64_t b = off[r], e = off[r + 1];
+        const uint32_t d = (uint32_t)(e - b);
+        const unsigned long long w = d ? wscan[e - 1] - (b ? wscan[b - 1] : 0ull) : 0ull;
+        if (d < 2 || w == 0 || caps.force_hub || caps.force_big || caps.force_wg || d > caps.wave_cap) continue;
+        ++wc;
+        pc += (d <= caps.pack_cap && w <= kPackMaxWork) ? 1u : 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        wc += __shfl_xor(wc, o);
+        pc += __shfl_xor(pc, o);
+    }
+    if ((threadIdx.x & 63) == 0 && wc) {
+        atomicAdd(&meta->wave_cands, wc);
+        atomicAdd(&meta->pack_cands, pc);
+    }
+}
+
 // One thread per vertex: d+, W(u) = sum of d+(v) over v in N+(u) (from the
 // inclusive scan of d+(col[e]) over the edges), bin, and the sort key
 // (bin << 24 | reversed work, clamped to 24 bits).  Bins: 0 global-memory table (too large for
@@ -265,6 +289,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
     if (threadIdx.x == 0) { s_w = 0; s_max = 0; }
     __syncthreads();
     const unsigned long long kWorkMax = (1ull << 24) - 1;  // larger work ties: LPT order is a heuristic
+    const uint32_t pack_cap = (caps.pack_cap && 2ull * meta->pack_cands >= meta->wave_cands) ? caps.pack_cap : 0u;
     // Per-thread partials, reduced across the wave, then one LDS atomic per wave.
     unsigned long long wsum = 0;
     uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0, nb5 = 0;
@@ -277,7 +302,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         else if (caps.force_hub || d > caps.big_cap) bin = 0;
         else if (caps.force_big || d > caps.wg_cap) bin = 1;
         else if (caps.force_wg || d > caps.wave_cap) bin = 2;
-        else if (d <= caps.pack_cap && w <= kPackMaxWork) bin = 4;
+        else if (d <= pack_cap && w <= kPackMaxWork) bin = 4;
         else bin = 3;
         const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
         skey[r] = ((unsigned long long)bin << 24) | (caps.lpt ? (kWorkMax - wk) : 0ull);
@@ -624,6 +649,11 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
         tmp = t.sort_tmp_bytes;
         TC_TRY(rocprim::inclusive_scan(t.sort_tmp, tmp, heads, wscan, (size_t)m_in,
                                        rocprim::plus<unsigned long long>(), stream));
+    }
+    if (caps.pack_cap) {
+        hipLaunchKernelGGL(k_pack_census, dim3(std::min(grid_for(n), 1024u)), dim3(kThreads), 0, stream, g.off, wscan,
+                           n, caps, g.meta);
+        TC_TRY(hipGetLastError());
     }
     // at most 1024 blocks: each block ends with a few global atomics on the same summary words
     hipLaunchKernelGGL(k_schedule, dim3(std::min(grid_for(n), 1024u)), dim3(kThreads), 0, stream, g.off, wscan, n, caps, g.meta,

@@ -82,8 +82,9 @@ typedef struct tc_params {
 #define TC_F_SUBWAVE_16  0x200u  /* groups of 16 lanes */
 #define TC_F_SUBWAVE_32  0x400u  /* groups of 32 lanes */
 #define TC_F_WAVE_LIST   0x800u  /* one list per wavefront at a time (warp-centric) */
-#define TC_F_NO_PACK     0x1000u /* no packed bin: one wavefront per light vertex (default: vertices with
-                                    out-degree <= 32 and W(u) <= 1024 share wavefronts, 4 x 16 lanes when
+#define TC_F_NO_PACK     0x1000u /* no packed bin: one wavefront per light vertex (default: when vertices
+                                    with out-degree <= 32 and W(u) <= 512 are at least half of the
+                                    wavefront-size tables, they share wavefronts, 4 x 16 lanes when
                                     out-degrees are <= 16, else 2 x 32 lanes) */
 
 /* Opaque handles. */
@@ -103,7 +104,8 @@ typedef struct tc_graph_info {
     uint32_t wg_cap;
     uint32_t n_big;       /* vertices in the large-LDS bin (one workgroup per CU with all of its LDS) */
     uint32_t big_cap;     /* out-degree limit of the large-LDS bin */
-    uint32_t n_packed;    /* light vertices (out-degree <= 32, W(u) <= 1024) packed 2-4 to a wavefront */
+    uint32_t n_packed;    /* light vertices (out-degree <= 32, W(u) <= 512) packed 2-4 to a wavefront; only
+                             when they are at least half of the wavefront-size tables */
     uint32_t reserved;
 } tc_graph_info;
 
@@ -152,7 +154,8 @@ tc_status tc_graph_build(tc_context* ctx, uint32_t n, uint64_t m_in, const uint3
                          void* d_temp, uint64_t temp_bytes, void* stream, tc_graph** out);
 
 /* Device scratch bytes one tc_graph_count call needs (per-vertex staging,
- * queue heads, global-memory tables for the hub bin). */
+ * queue heads, global-memory tables for the bin of vertices too large for any
+ * LDS table). */
 tc_status tc_count_scratch_bytes(const tc_context* ctx, uint32_t n, uint64_t m_in, uint64_t* bytes);
 
 /* Count the triangles of a built graph.  Asynchronous: the total is written

@@ -96,3 +96,39 @@ def test_algorithmic_bytes_formula():
 def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_tuner_flag_knobs_compose():
+    """The vertex-order and intra-vertex knobs live in the flags: setting one keeps the other bits,
+    and every combination the space can produce is accepted by the library's parameter check."""
+    from paper_2103_08053_amd import Params, autotune
+    from paper_2103_08053_amd.tc import _Params, load_library
+    p = Params(flags=0x1)  # keep rank order
+    q = autotune._with(autotune._with(p, "order", 0x80), "intra", 0x200)
+    assert q.flags == 0x1 | 0x80 | 0x200
+    assert autotune._get(q, "order") == 0x80 and autotune._get(q, "intra") == 0x200
+    q = autotune._with(q, "order", 0x40)
+    assert q.flags == 0x1 | 0x40 | 0x200
+    assert autotune._get(q, "slots_per_bucket") == q.slots_per_bucket
+    lib = load_library()
+    import ctypes
+    for order in autotune.SPACE["order"]:
+        for intra in autotune.SPACE["intra"]:
+            cp = _Params()
+            lib.tc_default_params(ctypes.byref(cp))
+            cp.flags = order | intra
+            h = ctypes.c_void_p()
+            # parameters are checked before any device is touched
+            st = lib.tc_create(0, ctypes.byref(cp), ctypes.byref(h))
+            assert st != 1, (order, intra)  # TC_E_INVALID would mean the check rejects them
+            if st == 0:
+                lib.tc_destroy(h)
+
+
+def test_measured_traffic_needs_matching_source_workload_and_mode():
+    import bench
+    t = bench.measured_traffic(True, "rmat22")
+    if t is not None:  # profile taken on the current kernel source
+        assert t > 0
+    assert bench.measured_traffic(True, "er25") is None
+    assert bench.measured_traffic(False, "rmat22") is None

@@ -6,7 +6,9 @@
 //     LDS): bin 0, out-degree too large for any LDS table, table in a
 //     global-memory region of the workgroup; bin 1, table in the LDS;
 //   * main launch: bin 2, the whole workgroup with the table in its LDS;
-//     bin 3, one 64-lane wavefront with the table in its slice of the LDS.
+//     bin 3, one 64-lane wavefront with the table in its slice of the LDS;
+//     bin 4, light vertices 4 (16 lanes each) or 2 (32 lanes each) to a
+//     wavefront, each table in a quarter of the slice.
 // This is the degree-aware resource assignment of Section 4.3 (a CTA for
 // large vertices, a warp for small ones; vertices with fewer than two
 // out-neighbours skipped), with atomic dynamic work fetching (one vertex per
@@ -382,7 +384,7 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
 }
 
 // The same walk with a per-lane cursor and lane-by-lane chain lookups, for
-// tables in global memory (hub bin).
+// tables in global memory (bin 0: too large for any LDS table).
 template <int S, bool PV, int HK>
 __device__ __forceinline__ unsigned long long probe_range_global(const Probe& pr, uint32_t d, uint32_t lo,
                                                                  uint32_t hi, int lane) {

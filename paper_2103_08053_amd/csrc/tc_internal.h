@@ -120,7 +120,7 @@ struct GraphDev {
     int64_t* off;       // [n + 1] CSR offsets of the oriented graph
     uint32_t* col;      // [m_in] out-neighbour lists (first meta->m entries used)
     uint32_t* rank;     // [n] input id -> rank
-    uint32_t* items;    // [n] scheduled vertices: hub bin, workgroup bin, wavefront bin, skipped
+    uint32_t* items;    // [n] scheduled vertices by bin (global table, large LDS, workgroup, wavefront, packed, skipped)
     uint32_t* gid;      // [n] graph index of each rank (batches only, else null)
 };
 

@@ -4,20 +4,23 @@
 //     self-loops and out-of-range ids become a sentinel that sorts last
 //     (cleaning rules of the paper, Section 2.6: duplicates and self-loops
 //     removed, directed pairs read as undirected);
-//  2. radix sort + unique: the undirected edge set;
-//  3. degree of every vertex, then its rank in (degree, id) order;
+//  2. radix sort; distinct edges numbered by a scan of first-of-run flags
+//     (duplicates stay in place and are skipped downstream);
+//  3. degree of every vertex (from runs of the sorted lower and upper
+//     endpoints), then its rank in (degree, id) order;
 //  4. orientation by rank-by-degree (Section 2.2): the edge runs from the
 //     lower-ranked to the higher-ranked endpoint, and every id is replaced by
 //     its rank, so out-neighbour lists hold ranks and hashing the low bits of
 //     a rank spreads neighbours of similar degree over consecutive buckets
-//     (the reordering idea of Section 4.1);
-//  5. CSR: radix sort of the oriented keys, row lengths from key runs, scan
-//     (int64 offsets); lists come out sorted by rank;
+//     (the reordering idea of Section 4.1; other orders are optional);
+//  5. CSR: stable radix sort of the oriented keys by row, row lengths from key
+//     runs, scan (int64 offsets);
 //  6. scheduling (Section 4.3): out-degree d+ and collective work
 //     W(u) = sum of d+(v) over out-neighbours v (the collective degree of
-//     Equation 2); vertices with d+ < 2 or W = 0 are skipped, the rest go to
-//     a global-memory-table bin, a workgroup bin or a wavefront bin by d+,
-//     and each bin is ordered by decreasing W (largest work first).
+//     Equation 2); vertices with d+ < 2 or W = 0 are skipped, the rest go by
+//     d+ to a global-memory-table bin, a large-LDS bin, a workgroup bin, a
+//     wavefront bin or (light vertices, when they dominate) a packed bin, and
+//     each bin is ordered by decreasing W (largest work first).
 #include <algorithm>
 #include <cstring>
 

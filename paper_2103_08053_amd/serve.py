@@ -15,7 +15,10 @@ loop, on one host thread:
   as budget and pipeline slots free up, and their build overlaps the count
   of the batches ahead of them;
 * retires a batch when its count event has completed: every request in it
-  is answered, its device memory returns to the budget.
+  is answered, its device memory returns to the budget;
+* when the device is idle and exactly one request waits, answers it directly
+  through tc_count (no batch set-up: at low load this is the lower-latency
+  path), unless ``direct_when_idle`` is off.
 
 Latency of a request = time its answer is available on the host - its
 scheduled arrival time.  :func:`serve_fifo` is the plain baseline: one
@@ -65,7 +68,7 @@ def make_request(rid: int, n: int, src, dst) -> Request:
 
 class Server:
     def __init__(self, device: int = 0, params: Params | None = None, hbm_budget: int = 64 << 30,
-                 max_batch: int = 256, max_inflight: int = 3):
+                 max_batch: int = 256, max_inflight: int = 3, direct_when_idle: bool = True):
         import torch
         self.torch = torch
         self.ctx = Context(device, params)
@@ -75,6 +78,7 @@ class Server:
         self.hbm_budget = hbm_budget
         self.max_batch = max_batch
         self.max_inflight = max_inflight
+        self.direct_when_idle = direct_when_idle
 
     def footprint(self, n_total: int, m_total: int, k: int) -> int:
         s, t = self.ctx.batch_footprint(max(k, 1), n_total, m_total)
@@ -106,6 +110,7 @@ class Server:
         nxt = 0
         done = 0
         batches = 0
+        direct = 0
         busy = 0.0  # host-observed time with at least one batch on the device
         t0 = time.perf_counter()
         last = 0.0
@@ -130,6 +135,18 @@ class Server:
                 done += len(f.reqs)
                 used -= f.bytes
                 f.batch.release()
+            # idle device, one waiting request: answer it directly
+            if self.direct_when_idle and not inflight and len(pending) == 1:
+                r = pending.popleft()
+                t_start = time.perf_counter()
+                r.total, _ = self.ctx.count(r.src.to(self.dev, non_blocking=True),
+                                            r.dst.to(self.dev, non_blocking=True), r.n)
+                r.done = time.perf_counter() - t0
+                busy += r.done - (t_start - t0)
+                last = r.done
+                done += 1
+                direct += 1
+                continue
             # admit a new batch
             if pending and len(inflight) < self.max_inflight:
                 take, n_tot, m_tot = [], 0, 0
@@ -158,7 +175,8 @@ class Server:
             else:
                 time.sleep(idle_sleep)
         wall = time.perf_counter() - t0
-        out = summarize(requests, wall, batches)
+        out = summarize(requests, wall, batches + direct)
+        out["direct"] = direct
         out["device_busy_frac"] = busy / wall
         return out
 

@@ -68,3 +68,19 @@ def test_autotune_prior_rejects_without_timing(tmp_path):
     say(f"[gpu] tuned {rep}")
     assert rep["skipped_by_prior"] == 3 and rep["evaluated"] == 2  # default + light_chunk=2
     assert rep["phi"] > 0 and rep["default_phi"] > 0
+
+
+def test_idle_requests_go_direct_and_match():
+    """Sparse arrivals find the device idle: those requests take the direct path; a burst is
+    batched; every answer equals the graph counted alone."""
+    from paper_2103_08053_amd import Context, serve
+    pool = [gg.rmat(11, 16, seed=2), gg.barabasi_albert(5000, 6, seed=3), gg.complete(40)]
+    ctx = Context(0)
+    alone = [ctx.count(g.src, g.dst, g.n)[0] for g in pool]
+    arrivals = np.concatenate([np.arange(6) * 0.03, 0.25 + np.zeros(12)])  # sparse, then a burst
+    pinned = [serve.make_request(i, g.n, g.src, g.dst) for i, g in enumerate(pool)]
+    reqs = [serve.Request(i, pinned[i % 3].n, pinned[i % 3].src, pinned[i % 3].dst) for i in range(len(arrivals))]
+    stats = serve.Server(0, hbm_budget=2 << 30, max_batch=8).run(reqs, arrivals)
+    say(f"[gpu] {stats}")
+    assert all(r.total == alone[r.rid % 3] for r in reqs)
+    assert stats["direct"] >= 1 and stats["batches"] > stats["direct"]

@@ -374,8 +374,10 @@ def main():
                                                / ablation["edge_centric_ms"])
     ctx.timing(False)
     kernel_ms = float(np.mean(kms))
-    log(f"[bench] count kernel {kernel_ms:.3f} ms (min {min(kms):.3f}), build {np.mean(build_ms):.3f} ms, "
-        f"info {info}")
+    kernel_median_ms = float(np.median(kms))
+    log(f"[bench] count kernel {kernel_ms:.3f} ms (median {kernel_median_ms:.3f}, min {min(kms):.3f}), "
+        f"build {np.mean(build_ms):.3f} ms, info {info}")
+    work = graph.bin_work()
     intra = None
     if args.intra:
         intra = {"virtual_combination_ms": kernel_ms}
@@ -409,6 +411,9 @@ def main():
                             "wavefront": info.n_wave},
                    "params": vars(ctx.params)},
         "count_kernel_ms": kernel_ms,
+        "count_kernel_median_ms": kernel_median_ms,
+        "work_share_by_bin": {name: w_ / max(1, sum(work)) for name, w_ in
+                              zip(("global_table", "large_lds", "workgroup", "wavefront", "packed", "skipped"), work)},
         "count_only_teps": info.m / (kernel_ms * 1e-3),
         "build_ms": float(np.mean(build_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -171,6 +171,12 @@ tc_status tc_graph_count(tc_context* ctx, const tc_graph* g, uint64_t* d_total,
  * the build saw an id >= n. */
 tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out);
 
+/* Work per bin: work[b] = sum of W(u) (the collective degree, u's number of
+ * 2-hop probes) over the vertices of bin b, b = 0 global-memory table, 1
+ * large LDS table, 2 workgroup, 3 wavefront, 4 packed, 5 skipped; the sum is
+ * W+.  Synchronises `stream`. */
+tc_status tc_graph_bin_work(const tc_graph* g, void* stream, uint64_t work[6]);
+
 /* Free the handle (host memory only; the storage stays the caller's). */
 tc_status tc_graph_release(tc_graph* g);
 

@@ -586,6 +586,19 @@ tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out)
     return TC_OK;
 }
 
+tc_status tc_graph_bin_work(const tc_graph* g, void* stream, uint64_t work[6]) {
+    if (!g || !work) return TC_E_INVALID;
+    for (int i = 0; i < 6; ++i) work[i] = 0;
+    if (g->empty) return TC_OK;
+    tc::GraphMeta m;
+    if (hipSetDevice(g->ctx->device) != hipSuccess) return TC_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(&m, g->dev.meta, sizeof(m), hipMemcpyDeviceToHost, st) != hipSuccess) return TC_E_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return TC_E_DEVICE;
+    for (int i = 0; i < 6; ++i) work[i] = m.bin_work[i];
+    return TC_OK;
+}
+
 tc_status tc_graph_release(tc_graph* g) {
     if (!g) return TC_OK;
     drop_capture(g);

@@ -33,7 +33,8 @@ struct GraphMeta {
     // no 2-hop work)
     unsigned int bins[6];
     unsigned int wave_cands, pack_cands;  // census before binning: wavefront-size tables, and packable ones
-    unsigned int pad[49];
+    unsigned long long bin_work[6];       // sum of W(u) over the vertices of each bin
+    unsigned int pad[36];
 };
 static_assert(sizeof(GraphMeta) == 256, "meta is one 256-byte block");
 

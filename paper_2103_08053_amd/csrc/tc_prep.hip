@@ -288,7 +288,11 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
                            BinCaps caps, GraphMeta* meta, unsigned long long* __restrict__ skey) {
     __shared__ unsigned long long s_w;
     __shared__ unsigned int s_max, s_bins[6];
-    if (threadIdx.x < 6) s_bins[threadIdx.x] = 0;
+    __shared__ unsigned long long s_bw[6];
+    if (threadIdx.x < 6) {
+        s_bins[threadIdx.x] = 0;
+        s_bw[threadIdx.x] = 0;
+    }
     if (threadIdx.x == 0) { s_w = 0; s_max = 0; }
     __syncthreads();
     const unsigned long long kWorkMax = (1ull << 24) - 1;  // larger work ties: LPT order is a heuristic
@@ -296,6 +300,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
     // Per-thread partials, reduced across the wave, then one LDS atomic per wave.
     unsigned long long wsum = 0;
     uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0, nb5 = 0;
+    unsigned long long bw[6] = {0, 0, 0, 0, 0, 0};
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         const int64_t b = off[r], e = off[r + 1];
         const uint32_t d = (uint32_t)(e - b);
@@ -310,6 +315,8 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
         skey[r] = ((unsigned long long)bin << 24) | (caps.lpt ? (kWorkMax - wk) : 0ull);
         wsum += w;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) bw[q] += (bin == (uint32_t)q) ? w : 0ull;
         dmax = d > dmax ? d : dmax;
         nb0 += bin == 0;
         nb1 += bin == 1;
@@ -320,6 +327,8 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
     }
     for (int o = 32; o > 0; o >>= 1) {
         wsum += __shfl_xor(wsum, o);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) bw[q] += __shfl_xor(bw[q], o);
         const uint32_t dm = __shfl_xor(dmax, o);
         dmax = dm > dmax ? dm : dmax;
         nb0 += __shfl_xor(nb0, o);
@@ -338,12 +347,17 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         atomicAdd(&s_bins[3], nb3);
         atomicAdd(&s_bins[4], nb4);
         atomicAdd(&s_bins[5], nb5);
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            if (bw[q]) atomicAdd(&s_bw[q], bw[q]);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(&meta->wplus, s_w);
         atomicMax(&meta->max_dplus, s_max);
         for (int i = 0; i < 6; ++i) atomicAdd(&meta->bins[i], s_bins[i]);
+        for (int i = 0; i < 6; ++i)
+            if (s_bw[i]) atomicAdd(&meta->bin_work[i], s_bw[i]);
     }
 }
 

@@ -23,7 +23,7 @@ EXPORTS = [
     "tc_count_scratch_bytes", "tc_graph_count", "tc_graph_info_get", "tc_graph_release",
     "tc_timing_enable", "tc_timing_last", "tc_batch_footprint", "tc_batch_build", "tc_graph_count_each",
     "tc_graph_count_replay", "tc_graph_k", "tc_graph_count_shard", "tc_graph_collisions",
-    "tc_graph_count_simple",
+    "tc_graph_count_simple", "tc_graph_bin_work",
 ]
 
 
@@ -133,6 +133,7 @@ def load_library(path: str = LIB_PATH):
         "tc_graph_count_shard": [vp, vp, u32, u32, vp, vp, vp, u64, vp],
         "tc_graph_collisions": [vp, vp, i32, vp, u64, vp, ctypes.POINTER(_CollisionStats)],
         "tc_graph_count_simple": [vp, vp, u32, vp, vp, u64, vp],
+        "tc_graph_bin_work": [vp, vp, ctypes.POINTER(u64)],
         "tc_graph_k": [vp, ctypes.POINTER(u32)],
         "tc_timing_last": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
     }
@@ -344,6 +345,12 @@ class Graph:
         self.count_async(pv, stream, replay=replay, shard=shard)
         tot = self.totals_dev.cpu().tolist()
         return (tot[0] if self.k == 1 else tot), (pv[: self.n] if per_vertex else None)
+
+    def bin_work(self, stream=None) -> list[int]:
+        """Sum of W(u) per bin: global table, large LDS, workgroup, wavefront, packed, skipped."""
+        arr = (ctypes.c_uint64 * 6)()
+        _check(self.ctx.lib.tc_graph_bin_work(self.h, _stream_ptr(stream), arr), self.ctx.h)
+        return [int(x) for x in arr]
 
     def count_simple(self, edge_centric: bool = False, build_only: bool = False, stream=None) -> int:
         """Total from the plain vertex- or edge-centric design of Section 3.3 (construction ablation)."""

@@ -408,3 +408,17 @@ def test_packed_light_vertices_match_unpacked(torch):
     g = gs[1]
     graph = Context(0).build(g.src, g.dst, g.n)
     assert sum(graph.count(shard=(s, 3))[0] for s in range(3)) == oracle.count(g.n, g.src, g.dst).total
+
+
+def test_bin_work_sums_to_wedges(ctx, torch):
+    """Work per bin adds up to W+ (the oracle's 2-hop probe count), with work in every used bin."""
+    from paper_2103_08053_amd import Context, Params
+    g = gg.dirty(gg.rmat(14, 16, seed=9), seed=10)
+    r = oracle.count(g.n, g.src, g.dst)
+    for kw in (dict(), dict(wave_max_dplus=32), dict(wg_lds_bytes=4096, wg_waves=4), dict(flags=4)):
+        graph = Context(0, Params(**kw)).build(g.src, g.dst, g.n)
+        info, work = graph.info(), graph.bin_work()
+        assert sum(work) == r.wedges_plus == info.wedges_plus, kw
+        counts = [info.n_hub, info.n_big, info.n_wg, info.n_wave, info.n_packed]
+        for b in range(5):
+            assert (work[b] > 0) == (counts[b] > 0), (kw, b, work, counts)

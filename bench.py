@@ -93,17 +93,53 @@ def copy_calibration():
     del a, b
 
 
+def measured_copy_gbs(nbytes: int = 1 << 31, reps: int = 5) -> float:
+    """Device-to-device copy bandwidth (bytes read + written per second, GB/s), median of `reps`
+    copies of `nbytes`, HIP events on the current stream: the practical ceiling of a streaming kernel."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del a, b
+    ms.sort()
+    return 2 * nbytes / (ms[len(ms) // 2] * 1e-3) / 1e9
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, info, stride: int):
+    import graphgen.workloads as W
     import oracle
     r = oracle.count(g.n, g.src, g.dst, per_vertex=False, stride=stride)
     share = r.counted_wedges / max(1, info.wedges_plus)
     t_full = r.t_clean_s + r.t_count_s / max(share, 1e-12)
+    small = W.small_rmat()
+    r1 = oracle.count(small.n, small.src, small.dst, threads=1)
     return {
         "value": info.m / t_full, "unit": "TEPS (oriented edges/s)", "cores": r.threads, "kind": "oracle",
         "sample": (f"full clean+orient ({r.t_clean_s:.1f} s) of the same graph, merge counting on vertices with "
                    f"id % {stride} == 0 ({100 * share:.2f}% of the 2-hop work, {r.t_count_s:.1f} s), "
                    f"count time scaled by the work share"),
         "seconds_measured": round(r.t_clean_s + r.t_count_s, 2),
+        "cpu_model": cpu_model(),
+        "single_thread_rmat16_s": round(r1.t_clean_s + r1.t_count_s, 3),
+        "single_thread_rmat16_teps": r1.m / max(r1.t_clean_s + r1.t_count_s, 1e-12),
     }
 
 
@@ -397,6 +433,7 @@ def main():
 
     b_alg = algorithmic_bytes(g.n, info.m, info.wedges_plus, per_vertex)
     achieved = b_alg / (kernel_ms * 1e-3) / 1e9
+    copy_gbs = measured_copy_gbs()
     out = {
         "metric": METRIC,
         "value": info.m / step_s,
@@ -420,6 +457,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_vertex, args.workload),
                      "kernel": "tc_count_kernel (after tc_hub_kernel, both inside the events)",
                      "algorithmic_bytes": b_alg,
+                     "measured_copy_gbs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "kernel_source_sha1": kernel_source_sha1()},
     }
     if ablation:

@@ -274,7 +274,8 @@ def run_serve(args):
         reqs = [serve.Request(i, *pinned[i % len(pool)]) for i in range(len(arrivals))]
         torch.cuda.synchronize()
         if mode == "batched":
-            srv = serve.Server(0, hbm_budget=args.hbm_budget_gb << 30, max_batch=args.max_batch)
+            srv = serve.Server(0, hbm_budget=args.hbm_budget_gb << 30, max_batch=args.max_batch,
+                               max_inflight=args.max_inflight)
             stats = srv.run(reqs, arrivals)
         else:
             stats = serve.serve_fifo(Context(0), reqs, arrivals)
@@ -289,7 +290,8 @@ def run_serve(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"Poisson {args.rate}/s for {args.duration}s over {len(pool)} graphs (R-MAT scale "
                                f"10-{args.serve_max_scale} ef 16, BA n 1e3-1e6 k 4-16)",
-                   "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch},
+                   "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
+                   "max_inflight": args.max_inflight},
         "batched": res["batched"], "plain": res["plain"],
     }
     print(json.dumps(out), flush=True)
@@ -315,6 +317,7 @@ def main():
     ap.add_argument("--serve-max-scale", type=int, default=20)
     ap.add_argument("--hbm-budget-gb", type=int, default=96)
     ap.add_argument("--max-batch", type=int, default=256)
+    ap.add_argument("--max-inflight", type=int, default=2, help="serving: batches on the device at once")
     ap.add_argument("--flags", type=int, default=0, help="extra TC_F_* flags for the single-graph workloads "
                     "(e.g. 64: in-degree vertex order, 128: collective-degree order)")
     ap.add_argument("--collisions", action="store_true", help="also report the tables' collision statistics")

@@ -68,7 +68,7 @@ def make_request(rid: int, n: int, src, dst) -> Request:
 
 class Server:
     def __init__(self, device: int = 0, params: Params | None = None, hbm_budget: int = 64 << 30,
-                 max_batch: int = 256, max_inflight: int = 3, direct_when_idle: bool = True):
+                 max_batch: int = 256, max_inflight: int = 2, direct_when_idle: bool = True):
         import torch
         self.torch = torch
         self.ctx = Context(device, params)

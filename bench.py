@@ -50,7 +50,9 @@ def algorithmic_bytes(n: int, m: int, wplus: int, per_vertex: bool) -> int:
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2103_08053_amd", "csrc", "tc_count.hip")
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "tc_count_kernel_rmat22_pmc.md")
+def pmc_summary(workload: str) -> str:
+    """Committed FETCH_SIZE / WRITE_SIZE summary of the count kernel on this workload."""
+    return os.path.join(ROOT, "profiles", f"tc_count_kernel_{workload}_pmc.md")
 CALIB_BYTES = 1 << 30
 
 
@@ -62,10 +64,11 @@ def kernel_source_sha1() -> str:
 def measured_traffic(per_vertex: bool, workload: str):
     """DRAM-side bytes per count launch from the committed PMC summary, if it
     was taken on the current kernel source, workload and mode; else None."""
-    if not os.path.exists(PMC_SUMMARY):
+    path = pmc_summary(workload)
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(PMC_SUMMARY):
+    for line in open(path):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             kv[k.strip()] = v.strip().strip("`")

@@ -125,10 +125,24 @@ def test_tuner_flag_knobs_compose():
                 lib.tc_destroy(h)
 
 
-def test_measured_traffic_needs_matching_source_workload_and_mode():
+def test_measured_traffic_needs_matching_source_workload_and_mode(tmp_path, monkeypatch):
     import bench
-    t = bench.measured_traffic(True, "rmat22")
-    if t is not None:  # profile taken on the current kernel source
-        assert t > 0
+    for w in ("rmat22", "er25", "rmat26"):
+        t = bench.measured_traffic(True, w)
+        if t is not None:  # committed profile taken on the current kernel source
+            assert t > 0
+    assert bench.measured_traffic(True, "rmat16") is None  # no profile for it
+    f = tmp_path / "summary.md"
+    sha = bench.kernel_source_sha1()
+
+    def summary(src, mode, workload):
+        f.write_text(f"- kernel_source_sha1: `{src}`\n- per_vertex: {mode}\n- workload: {workload}\n"
+                     "- traffic_bytes_per_launch: 123\n")
+
+    monkeypatch.setattr(bench, "pmc_summary", lambda w: str(f))
+    summary(sha, True, "er25")
+    assert bench.measured_traffic(True, "er25") == 123
+    assert bench.measured_traffic(False, "er25") is None
+    assert bench.measured_traffic(True, "rmat22") is None
+    summary("0" * 40, True, "er25")
     assert bench.measured_traffic(True, "er25") is None
-    assert bench.measured_traffic(False, "rmat22") is None

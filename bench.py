@@ -49,16 +49,25 @@ def algorithmic_bytes(n: int, m: int, wplus: int, per_vertex: bool) -> int:
     return 8 * n + 4 * m + 16 * m + 4 * wplus + 8 + (8 * n if per_vertex else 0)
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_2103_08053_amd", "csrc", "tc_count.hip")
+# Sources the count kernels are compiled from (the kernel file and the headers it includes).
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2103_08053_amd", "csrc", f) for f in ("tc_count.hip", "tc_internal.h", "tc_wave.h")]
+
+
 def pmc_summary(workload: str) -> str:
     """Committed FETCH_SIZE / WRITE_SIZE summary of the count kernel on this workload."""
     return os.path.join(ROOT, "profiles", f"tc_count_kernel_{workload}_pmc.md")
+
+
 CALIB_BYTES = 1 << 30
 
 
 def kernel_source_sha1() -> str:
+    """SHA-1 over the count kernels' sources; a committed counter summary counts only if it matches."""
     import hashlib
-    return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
+    h = hashlib.sha1()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(per_vertex: bool, workload: str):

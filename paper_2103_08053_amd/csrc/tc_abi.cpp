@@ -149,6 +149,7 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     size_t o = 0;
     L.s_meta = o;  o = align_up(o + sizeof(tc::GraphMeta));
     L.s_off = o;   o = align_up(o + sizeof(int64_t) * ((size_t)n + 1));
+    L.s_off32 = o; o = align_up(o + sizeof(uint32_t) * ((size_t)n + 1));
     L.s_col = o;   o = align_up(o + sizeof(uint32_t) * (size_t)m_in);
     L.s_rank = o;  o = align_up(o + sizeof(uint32_t) * (size_t)n);
     L.s_items = o; o = align_up(o + sizeof(uint32_t) * (size_t)n);
@@ -191,6 +192,7 @@ tc::GraphDev graph_ptrs(void* storage, const Layout& L) {
     tc::GraphDev g;
     g.meta = reinterpret_cast<tc::GraphMeta*>(b + L.s_meta);
     g.off = reinterpret_cast<int64_t*>(b + L.s_off);
+    g.off32 = reinterpret_cast<uint32_t*>(b + L.s_off32);
     g.col = reinterpret_cast<uint32_t*>(b + L.s_col);
     g.rank = reinterpret_cast<uint32_t*>(b + L.s_rank);
     g.items = reinterpret_cast<uint32_t*>(b + L.s_items);
@@ -303,7 +305,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     }
     tc::CountArgs a{};
     a.meta = g->dev.meta;
-    a.off = g->dev.off;
+    a.off = g->dev.off32;
     a.col = g->dev.col;
     a.items = g->dev.items;
     a.heads = reinterpret_cast<uint32_t*>(b + L.c_heads);

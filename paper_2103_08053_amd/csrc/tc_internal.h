@@ -119,6 +119,7 @@ inline uint32_t capacity(uint32_t words, uint32_t S, uint32_t load_pct, bool pv)
 struct GraphDev {
     GraphMeta* meta;
     int64_t* off;       // [n + 1] CSR offsets of the oriented graph
+    uint32_t* off32;    // [n + 1] the same offsets in 32 bits (m_in < 2^31), read by the count kernels
     uint32_t* col;      // [m_in] out-neighbour lists (first meta->m entries used)
     uint32_t* rank;     // [n] input id -> rank
     uint32_t* items;    // [n] scheduled vertices by bin (global table, large LDS, workgroup, wavefront, packed, skipped)
@@ -159,7 +160,7 @@ struct BinCaps {
 struct Layout {
     size_t storage, temp, scratch;
     // storage offsets
-    size_t s_meta, s_off, s_col, s_rank, s_items, s_gid;
+    size_t s_meta, s_off, s_off32, s_col, s_rank, s_items, s_gid;
     // temp offsets
     size_t t_keys_a, t_keys_b, t_aux, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_rk_a, t_rk_b, t_off2, t_sort;
     size_t sort_tmp_bytes;
@@ -172,7 +173,7 @@ struct Layout {
 
 struct CountArgs {
     const GraphMeta* meta;
-    const int64_t* off;
+    const uint32_t* off;  // [n + 1] 32-bit CSR offsets (half the cache footprint of the 64-bit ones)
     const uint32_t* col;
     const uint32_t* items;
     uint32_t* heads;                 // [kHeadWords] queue heads (zeroed before the launches)

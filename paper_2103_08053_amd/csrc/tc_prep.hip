@@ -100,6 +100,13 @@ __device__ __forceinline__ bool first_of_run(const unsigned long long* keys, uin
     return k != sentinel && (i == 0 || keys[i - 1] != k);
 }
 
+// The CSR offsets narrowed to 32 bits for the count kernels (m_in < 2^31): at 2^25 vertices the
+// 64-bit array (268 MB) no longer fits the Infinity Cache, the 32-bit one (134 MB) does.
+__global__ void k_narrow(const int64_t* __restrict__ off, uint64_t n1, uint32_t* __restrict__ off32) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n1; i += (uint64_t)gridDim.x * blockDim.x)
+        off32[i] = (uint32_t)off[i];
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t words) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -687,6 +694,10 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
 
     // 5b (optional): hash ids in another vertex order.
     if (caps.order) TC_TRY(relabel(n, g, t, batch, caps.order, m_in, stream));
+
+    hipLaunchKernelGGL(k_narrow, dim3(grid_for((uint64_t)n + 1)), dim3(kThreads), 0, stream, g.off, (uint64_t)n + 1,
+                       g.off32);
+    TC_TRY(hipGetLastError());
 
     // 6: bins and largest-work-first order; W(u) from a scan of d+(col[e]).
     unsigned long long* wscan = reinterpret_cast<unsigned long long*>(t.keys_a);

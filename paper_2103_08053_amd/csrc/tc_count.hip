@@ -105,6 +105,12 @@ __device__ __forceinline__ unsigned long long ballot_has(const Bucket<S>& v, uin
     return m;
 }
 
+// This lane's bit of a wave mask, as a lane predicate (the mask itself is the predicate: no vector
+// shift, and, or compare of the 64-bit value).
+__device__ __forceinline__ bool lane_in(unsigned long long mask) {
+    return __builtin_amdgcn_inverse_ballot_w64(mask);
+}
+
 // Byte offset of w within a bucket that contains it (j * 4).
 template <int S>
 __device__ __forceinline__ uint32_t bucket_pos4(const Bucket<S>& v, uint32_t w) {
@@ -255,24 +261,24 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         const Bucket<S> v = read_bucket<S>(pr.slots, b);
         const unsigned long long hm = ballot_has<S>(v, pw) & mine;
         const unsigned long long cmask = __ballot(v.v[S - 1] != kEmpty) & mine & ~hm;
-        if constexpr (!PV) hits += (uint32_t)((hm >> lane) & 1ull);
+        if constexpr (!PV) hits += (uint32_t)lane_in(hm);
         if constexpr (PV) {
-            if ((hm >> lane) & 1ull) {
+            if (lane_in(hm)) {
                 tally_slot4<S>(pr, b, bucket_pos4<S>(v, pw));
                 atomicAdd(&pr.tally[pk], 1u);
                 ++hits;
             }
         }
-        pb = ((cmask >> lane) & 1ull) ? b : pb;
+        pb = lane_in(cmask) ? b : pb;
         pm = cmask;
     };
 
     auto resolve = [&](const Bucket<S>& v, uint32_t w, uint32_t b, uint32_t kk, unsigned long long actm) {
         const unsigned long long hm = ballot_has<S>(v, w) & actm;
         const unsigned long long cm = __ballot(v.v[S - 1] != kEmpty) & actm & ~hm;
-        if constexpr (!PV) hits += (uint32_t)(bucket_has<S>(v, w) & ((actm >> lane) & 1ull));
+        if constexpr (!PV) hits += (uint32_t)lane_in(hm);
         if constexpr (PV) {
-            const bool hit = bucket_has<S>(v, w) & ((actm >> lane) & 1ull);
+            const bool hit = lane_in(hm);
             if (kk != acck) {
                 if (accn) atomicAdd(&pr.tally[acck], accn);
                 hits += accn;
@@ -284,7 +290,7 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         }
         if (cm) {
             while (cm & pm) step_parked();
-            const bool cont = !bucket_has<S>(v, w) & (v.v[S - 1] != kEmpty) & ((actm >> lane) & 1ull);
+            const bool cont = lane_in(cm);
             pw = cont ? w : pw;
             pb = cont ? b : pb;
             if constexpr (PV) pk = cont ? kk : pk;

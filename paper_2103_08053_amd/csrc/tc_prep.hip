@@ -74,6 +74,25 @@ hipError_t sort_keys(void* tmp, size_t& bytes, uint32_t* in, uint32_t* out, size
     return rocprim::radix_sort_keys(tmp, bytes, in, out, count, lo, hi, stream);
 }
 
+// 32-bit keys with their original positions as values (per-vertex sorts), by the same rule.
+hipError_t sort_pairs(void* tmp, size_t& bytes, uint32_t* kin, uint32_t* kout, uint32_t* vout, size_t count,
+                      uint32_t hi, hipStream_t stream) {
+    const auto pos = rocprim::counting_iterator<uint32_t>(0);
+    if ((hi + 8) / 9 < (hi + 7) / 8)
+        return rocprim::radix_sort_pairs<Onesweep9x32>(tmp, bytes, kin, kout, pos, vout, count, 0, hi, stream);
+    return rocprim::radix_sort_pairs(tmp, bytes, kin, kout, pos, vout, count, 0, hi, stream);
+}
+
+// Bits of any vertex degree: at most min(n - 1, 2 m_in).
+uint32_t degree_bits(uint32_t n, uint64_t m_in) {
+    const uint64_t dmax = (uint64_t)n - 1 < 2 * m_in ? (uint64_t)n - 1 : 2 * m_in;
+    uint32_t b = 1;
+    while (b < 32 && (1ull << b) <= dmax) ++b;
+    return b;
+}
+
+constexpr uint32_t kScheduleBits = 27;  // schedule keys: bin (0-5) << 24 | 24-bit reversed work
+
 // 1 for the first key of each run of equal keys (and not the sentinel): the
 // inclusive scan of these flags numbers the distinct edges.
 struct FirstOfRun {
@@ -320,7 +339,7 @@ __global__ void k_pack_census(const int64_t* __restrict__ off, const unsigned lo
 // 2 workgroup LDS table, 3 wavefront LDS slice, 4 light vertices packed
 // several to a wavefront, 5 skipped.
 __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long long* __restrict__ wscan, uint32_t n,
-                           BinCaps caps, GraphMeta* meta, unsigned long long* __restrict__ skey) {
+                           BinCaps caps, GraphMeta* meta, uint32_t* __restrict__ skey) {
     __shared__ unsigned long long s_w;
     __shared__ unsigned int s_max, s_bins[6];
     __shared__ unsigned long long s_bw[6];
@@ -348,7 +367,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         else if (d <= pack_cap && w <= kPackMaxWork) bin = 4;
         else bin = 3;
         const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
-        skey[r] = ((unsigned long long)bin << 24) | (caps.lpt ? (kWorkMax - wk) : 0ull);
+        skey[r] = (bin << 24) | (uint32_t)(caps.lpt ? (kWorkMax - wk) : 0ull);
         wsum += w;
 #pragma unroll
         for (int q = 0; q < 6; ++q) bw[q] += (bin == (uint32_t)q) ? w : 0ull;
@@ -530,6 +549,12 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
         if (rocprim::radix_sort_pairs(nullptr, q, k64, k64, rocprim::counting_iterator<uint32_t>(0), u32p, (size_t)n, 0,
                                       64) == hipSuccess && q > best) best = q;
     }
+    sz = 0;
+    if (sort_pairs(nullptr, sz, u32p, u32p, u32p, (size_t)n, degree_bits(n, m_in), 0) == hipSuccess && sz > best)
+        best = sz;
+    sz = 0;
+    if (sort_pairs(nullptr, sz, u32p, u32p, u32p, (size_t)n, kScheduleBits, 0) == hipSuccess && sz > best) best = sz;
+    sz = 0;
     int64_t* i64p = nullptr;
     if (rocprim::exclusive_scan(nullptr, sz, u32p, i64p, (unsigned long long)0, (size_t)n + 1,
                                 rocprim::plus<unsigned long long>()) == hipSuccess && sz > best) best = sz;
@@ -643,15 +668,9 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
                            m_in, sentinel, g.meta, t.deg);
         TC_TRY(hipGetLastError());
     }
-    uint32_t deg_bits = 1;
-    {
-        const uint64_t dmax = (uint64_t)n - 1 < 2 * m_in ? (uint64_t)n - 1 : 2 * m_in;
-        while (deg_bits < 32 && (1ull << deg_bits) <= dmax) ++deg_bits;
-    }
     uint32_t* deg_sorted = reinterpret_cast<uint32_t*>(t.skey_a);
     tmp = t.sort_tmp_bytes;
-    TC_TRY(rocprim::radix_sort_pairs(t.sort_tmp, tmp, t.deg, deg_sorted, rocprim::counting_iterator<uint32_t>(0),
-                                     t.order, (size_t)n, 0, deg_bits, stream));
+    TC_TRY(sort_pairs(t.sort_tmp, tmp, t.deg, deg_sorted, t.order, (size_t)n, degree_bits(n, m_in), stream));
     hipLaunchKernelGGL(k_rank, dim3(grid_for(n)), dim3(kThreads), 0, stream, t.order, n, g.rank);
     TC_TRY(hipGetLastError());
     if (batch) {
@@ -714,12 +733,13 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
         TC_TRY(hipGetLastError());
     }
     // at most 1024 blocks: each block ends with a few global atomics on the same summary words
+    uint32_t* skey = reinterpret_cast<uint32_t*>(t.skey_a);
     hipLaunchKernelGGL(k_schedule, dim3(std::min(grid_for(n), 1024u)), dim3(kThreads), 0, stream, g.off, wscan, n, caps, g.meta,
-                       t.skey_a);
+                       skey);
     TC_TRY(hipGetLastError());
     tmp = t.sort_tmp_bytes;
-    TC_TRY(rocprim::radix_sort_pairs(t.sort_tmp, tmp, t.skey_a, t.skey_b, rocprim::counting_iterator<uint32_t>(0),
-                                     g.items, (size_t)n, 0, 27, stream));
+    TC_TRY(sort_pairs(t.sort_tmp, tmp, skey, reinterpret_cast<uint32_t*>(t.skey_b), g.items, (size_t)n, kScheduleBits,
+                      stream));
     return hipSuccess;
 }
 

@@ -43,10 +43,23 @@ def workload(name: str):
 
 
 def algorithmic_bytes(n: int, m: int, wplus: int, per_vertex: bool) -> int:
-    """Bytes the count kernel must move with no cache reuse: u's offsets (8n),
-    its list for the table (4m), each out-neighbour's offset pair (16m), every
-    2-hop id (4 W+), the total (8) and, with per-vertex output, 8n more."""
-    return 8 * n + 4 * m + 16 * m + 4 * wplus + 8 + (8 * n if per_vertex else 0)
+    """Bytes the count kernel must move with no cache reuse, with the 32-bit CSR offsets the count
+    kernels read: u's offset pair (4n: consecutive vertices share their bounds), u's list for the
+    table (4m), each out-neighbour's offset pair (8m), every 2-hop id (4 W+), the total (8) and, with
+    per-vertex output, the counts (8n)."""
+    return 4 * n + 4 * m + 8 * m + 4 * wplus + 8 + (8 * n if per_vertex else 0)
+
+
+# Vector-instruction issue ceiling: 256 CUs x 4 SIMDs, one 64-lane vector instruction per SIMD every
+# 4 cycles (16 lanes per cycle), 2.4 GHz.
+SIMDS = 1024
+CLOCK_HZ = 2.4e9
+VALU_ISSUE_PER_S = SIMDS * CLOCK_HZ / 4
+
+
+def sq_summary(workload: str) -> str:
+    """Committed instruction-counter summary of the count kernel on this workload."""
+    return os.path.join(ROOT, "profiles", f"tc_count_kernel_{workload}_sq.md")
 
 
 # Sources the count kernels are compiled from (the kernel file and the headers it includes).
@@ -70,10 +83,9 @@ def kernel_source_sha1() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(per_vertex: bool, workload: str):
-    """DRAM-side bytes per count launch from the committed PMC summary, if it
-    was taken on the current kernel source, workload and mode; else None."""
-    path = pmc_summary(workload)
+def summary_fields(path: str, per_vertex: bool, workload: str):
+    """`- key: value` lines of a committed counter summary, if it was taken on the current kernel
+    source, this workload and this output mode; else None."""
     if not os.path.exists(path):
         return None
     kv = {}
@@ -87,10 +99,32 @@ def measured_traffic(per_vertex: bool, workload: str):
         return None
     if kv.get("workload") != workload:
         return None
+    return kv
+
+
+def measured_traffic(per_vertex: bool, workload: str):
+    """Bytes past the L2 per count launch (reads and writes between the L2 and the memory fabric,
+    Infinity Cache hits included) from the committed PMC summary, or None."""
+    kv = summary_fields(pmc_summary(workload), per_vertex, workload)
     try:
-        return int(kv["traffic_bytes_per_launch"])
+        return int(kv["traffic_bytes_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
+
+
+def issue_ceiling(per_vertex: bool, workload: str, kernel_ms: float):
+    """Vector-issue floor of the count launch: its measured vector instructions (committed SQ
+    summary of the same source, workload and mode) issued at one per SIMD every 4 cycles."""
+    kv = summary_fields(sq_summary(workload), per_vertex, workload)
+    if not kv:
+        return None
+    try:
+        valu = float(kv["valu_insts_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    floor_ms = valu / VALU_ISSUE_PER_S * 1e3
+    return {"valu_insts_per_launch": valu, "valu_issue_per_s": VALU_ISSUE_PER_S, "floor_ms": floor_ms,
+            "frac": floor_ms / kernel_ms, "source": os.path.relpath(sq_summary(workload), ROOT)}
 
 
 def copy_calibration():
@@ -135,24 +169,33 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(g, info, stride: int):
+def cpu_baseline(g, info, total: int, stride: int = 1):
+    """The oracle timed on this host: clean, orient and merge-count the whole graph (stride 1), the
+    work of one step, unscaled.  A larger stride counts only vertices with id % stride == 0 and is
+    reported as a partial sample, never as the value."""
     import graphgen.workloads as W
     import oracle
     r = oracle.count(g.n, g.src, g.dst, per_vertex=False, stride=stride)
-    share = r.counted_wedges / max(1, info.wedges_plus)
-    t_full = r.t_clean_s + r.t_count_s / max(share, 1e-12)
+    secs = r.t_clean_s + r.t_count_s
+    if stride == 1:
+        assert r.total == total and r.m == info.m, (r.total, total)
     small = W.small_rmat()
     r1 = oracle.count(small.n, small.src, small.dst, threads=1)
-    return {
-        "value": info.m / t_full, "unit": "TEPS (oriented edges/s)", "cores": r.threads, "kind": "oracle",
-        "sample": (f"full clean+orient ({r.t_clean_s:.1f} s) of the same graph, merge counting on vertices with "
-                   f"id % {stride} == 0 ({100 * share:.2f}% of the 2-hop work, {r.t_count_s:.1f} s), "
-                   f"count time scaled by the work share"),
-        "seconds_measured": round(r.t_clean_s + r.t_count_s, 2),
+    out = {
+        "value": info.m / secs if stride == 1 else None, "unit": "TEPS (oriented edges/s)", "cores": r.threads,
+        "kind": "oracle",
+        "sample": (f"the whole graph, one pass: clean + orient {r.t_clean_s:.1f} s, merge count {r.t_count_s:.1f} s"
+                   if stride == 1 else
+                   f"clean + orient the whole graph ({r.t_clean_s:.1f} s), merge count of the vertices with id % "
+                   f"{stride} == 0 only ({100 * r.counted_wedges / max(1, info.wedges_plus):.2f}% of the 2-hop "
+                   f"work, {r.t_count_s:.1f} s); not a whole-graph rate"),
+        "seconds_measured": round(secs, 2), "clean_orient_s": round(r.t_clean_s, 2),
+        "count_s": round(r.t_count_s, 2), "same_total_as_gpu": r.total == total if stride == 1 else None,
         "cpu_model": cpu_model(),
         "single_thread_rmat16_s": round(r1.t_clean_s + r1.t_count_s, 3),
         "single_thread_rmat16_teps": r1.m / max(r1.t_clean_s + r1.t_count_s, 1e-12),
     }
+    return out
 
 
 def run_batch(args):
@@ -316,7 +359,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--no-per-vertex", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=16)
+    ap.add_argument("--cpu-stride", type=int, default=1,
+                    help="oracle baseline on vertices with id %% stride == 0 only (1: the whole graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="run a 1 GiB device copy first (for scaling PMC byte counters)")
@@ -470,9 +514,14 @@ def main():
         "build_ms": float(np.mean(build_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_vertex, args.workload),
+                     "traffic_kind": "bytes between the L2 and the memory fabric (FETCH_SIZE + WRITE_SIZE scaled "
+                                     "by a device copy); Infinity Cache hits included, so not DRAM bytes",
+                     "achieved_kind": "algorithmic bytes / kernel time (no cache reuse assumed: re-reads served "
+                                      "by the L2 or the Infinity Cache count as if they came from HBM)",
                      "kernel": "tc_count_kernel (after tc_hub_kernel, both inside the events)",
                      "algorithmic_bytes": b_alg,
                      "measured_copy_gbs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
+                     "issue": issue_ceiling(per_vertex, args.workload, kernel_ms),
                      "kernel_source_sha1": kernel_source_sha1()},
     }
     if ablation:
@@ -487,7 +536,7 @@ def main():
         log(f"[bench] shards: {shards}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(g, info, args.cpu_stride)
+        out["cpu_baseline"] = cpu_baseline(g, info, total, args.cpu_stride)
         log(f"[bench] cpu baseline done: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 

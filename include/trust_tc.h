@@ -267,6 +267,24 @@ tc_status tc_graph_count_replay(tc_context* ctx, tc_graph* g, uint64_t* d_totals
 /* Number of graphs (k) of a built graph or batch. */
 tc_status tc_graph_k(const tc_graph* g, uint32_t* k);
 
+/* ---------------------------------------------------------------- host-side helpers (no device work)
+ * tc_vc_locate: the index map of virtual combination (paper Section 4.2),
+ * evaluated on the host by the same code the count kernels run on the
+ * device.  The out-neighbour lists N+(v_0..v_{d-1}) of a vertex are read as
+ * one flattened sequence; incl_prefix[k] = |N+(v_0)| + ... + |N+(v_k)| (host
+ * array of d entries, non-decreasing).  Flattened index `index` belongs to
+ * list *owner = the first k with incl_prefix[k] > index, at position *offset =
+ * index - incl_prefix[k - 1] (index itself for k = 0).  TC_E_INVALID when a
+ * pointer is null, d = 0 or index >= incl_prefix[d - 1].
+ *
+ * tc_wide_list_addressing: whether a count of a graph with m_in edge samples
+ * walks the lists with 64-bit word addressing (*wide = 1) instead of 32-bit
+ * byte offsets (*wide = 0).  Wide when 4 * m_in + 256 >= 2^32 (a lane may
+ * step 256 bytes past the last list before it moves on) or when `flags`
+ * holds TC_F_WIDE_ADDR.  TC_E_INVALID when wide is null. */
+tc_status tc_vc_locate(const uint32_t* incl_prefix, uint32_t d, uint32_t index, uint32_t* owner, uint32_t* offset);
+tc_status tc_wide_list_addressing(uint64_t m_in, uint32_t flags, int* wide);
+
 /* ---------------------------------------------------------------- timing
  * With timing on, every tc_count / tc_graph_build / tc_graph_count records
  * HIP events on its stream around its device steps (events owned by ctx).

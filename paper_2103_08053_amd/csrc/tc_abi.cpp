@@ -293,11 +293,11 @@ bool needs_hub_launch(const tc_graph* g) {
 
 // The count: clears, the persistent kernel and (per-vertex mode) the gather.
 // d_totals has g->k entries.  With `record` false no timing events are recorded (stream capture).
-tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex, void* scratch,
+tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex, void* d_scr,
                      const Layout& L, hipStream_t s, bool record = true, uint32_t shard = 0, uint32_t shards = 1) {
     const tc_params& p = g->p;
     const bool pv = d_per_vertex != nullptr;
-    char* b = static_cast<char*>(scratch);
+    char* b = static_cast<char*>(d_scr);
     if (g->empty) {
         HIP_TRY(ctx, tc::fill_u32(d_totals, 0, 2 * (size_t)g->k, s));
         if (pv) HIP_TRY(ctx, tc::fill_u32(d_per_vertex, 0, 2 * (size_t)g->n, s));
@@ -319,7 +319,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.slice_words = slice_words(p);
     a.lrecip = tc::load_recip(p.load_factor_pct);
     a.chunk = p.light_chunk;
-    a.wide = (g->m_in >= (1ull << 30)) || (p.flags & TC_F_WIDE_ADDR) ? 1u : 0u;
+    a.wide = tc::wide_list_addressing(g->m_in, (p.flags & TC_F_WIDE_ADDR) != 0) ? 1u : 0u;
     a.shard = shard;
     a.shards = shards;
     a.subwave = subwave_lanes(p.flags);
@@ -353,6 +353,9 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     if (pv) HIP_TRY(ctx, tc::gather_per_vertex(a.tv, g->dev.rank, g->n, reinterpret_cast<unsigned long long*>(d_per_vertex), s));
     return TC_OK;
 }
+
+tc_status count_one_shot(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d_src, const uint32_t* d_dst,
+                         uint64_t* d_per_vertex, void* d_ws, const Layout& L, hipStream_t st, uint64_t* h_total);
 
 void drop_capture(tc_graph* g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -515,13 +518,24 @@ tc_status tc_count(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d
         return fail(ctx, TC_E_NOMEM, "workspace %llu bytes < %llu needed", (unsigned long long)ws_bytes,
                     (unsigned long long)need);
     if (tc_status s = use_device(ctx)) return s;
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    return count_one_shot(ctx, n, m_in, d_src, d_dst, d_per_vertex, d_ws, L, static_cast<hipStream_t>(stream),
+                          h_total);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Clean, build and count in the workspace `d_ws` laid out by L (storage | temp | scratch), then read
+// the total and the range flag back (synchronises the stream).
+tc_status count_one_shot(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d_src, const uint32_t* d_dst,
+                         uint64_t* d_per_vertex, void* d_ws, const Layout& L, hipStream_t st, uint64_t* h_total) {
     char* ws = static_cast<char*>(d_ws);
     tc_graph g;
     if (tc_status s = build_into(ctx, &g, n, m_in, d_src, d_dst, ws, ws + L.storage, L, st)) return s;
-    void* scratch = ws + L.storage + L.temp;
-    uint64_t* d_total = reinterpret_cast<uint64_t*>(static_cast<char*>(scratch) + L.c_total);
-    if (tc_status s = count_into(ctx, &g, d_total, d_per_vertex, scratch, L, st)) return s;
+    char* d_scr = ws + L.storage + L.temp;
+    uint64_t* d_total = reinterpret_cast<uint64_t*>(d_scr + L.c_total);
+    if (tc_status s = count_into(ctx, &g, d_total, d_per_vertex, d_scr, L, st)) return s;
     uint64_t host[2] = {0, 0};
     HIP_TRY(ctx, hipMemcpyAsync(&host[0], d_total, 8, hipMemcpyDeviceToHost, st));
     unsigned int err = 0;
@@ -531,6 +545,10 @@ tc_status tc_count(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d
     *h_total = host[0];
     return TC_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 tc_status tc_graph_build(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d_src, const uint32_t* d_dst,
                          void* d_storage, uint64_t storage_bytes, void* d_temp, uint64_t temp_bytes, void* stream,
@@ -605,6 +623,20 @@ tc_status tc_graph_release(tc_graph* g) {
     if (!g) return TC_OK;
     drop_capture(g);
     delete g;
+    return TC_OK;
+}
+
+tc_status tc_vc_locate(const uint32_t* incl_prefix, uint32_t d, uint32_t index, uint32_t* owner, uint32_t* offset) {
+    if (!incl_prefix || !owner || !offset || d == 0 || index >= incl_prefix[d - 1]) return TC_E_INVALID;
+    const uint32_t k = tc::vc_owner(d, index, [&](uint32_t j) { return incl_prefix[j]; });
+    *owner = k;
+    *offset = index - (k ? incl_prefix[k - 1] : 0u);
+    return TC_OK;
+}
+
+tc_status tc_wide_list_addressing(uint64_t m_in, uint32_t flags, int* wide) {
+    if (!wide) return TC_E_INVALID;
+    *wide = tc::wide_list_addressing(m_in, (flags & TC_F_WIDE_ADDR) != 0) ? 1 : 0;
     return TC_OK;
 }
 

@@ -216,12 +216,7 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
     {
         const uint32_t ii0 = lo + (uint32_t)lane;
         const uint32_t key = ii0 < hi ? ii0 : hi - 1;
-        uint32_t l = 0, r = d - 1;
-        while (l < r) {
-            const uint32_t mid = (l + r) >> 1;
-            if (pr.P[mid].x > key) r = mid; else l = mid + 1;
-        }
-        k = l;
+        k = vc_owner(d, key, [&](uint32_t j) { return pr.P[j].x; });
         const u32x2 rec = pr.P[k];
         base = rec.y;
         pos = base + ii0;
@@ -399,12 +394,7 @@ __device__ __forceinline__ unsigned long long probe_range_global(const Probe& pr
     uint32_t i = lo + (uint32_t)lane;
     uint32_t k = 0, end = 0, base = 0;
     if (i < hi) {
-        uint32_t l = 0, r = d - 1;
-        while (l < r) {
-            const uint32_t mid = (l + r) >> 1;
-            if (pr.P[mid].x > i) r = mid; else l = mid + 1;
-        }
-        k = l;
+        k = vc_owner(d, i, [&](uint32_t j) { return pr.P[j].x; });
         const u32x2 rec = pr.P[k];
         end = rec.x;
         base = rec.y;
@@ -656,12 +646,7 @@ __device__ __forceinline__ void process_packed(const CountArgs& a, uint32_t ug, 
     const uint32_t maxsteps = __builtin_amdgcn_readfirstlane(m);
     uint32_t k = 0, cur = 0, end = 0, hits = 0;
     if (gl < W) {
-        uint32_t l = 0, r = d - 1;
-        while (l < r) {
-            const uint32_t mid = (l + r) >> 1;
-            if (P[mid].x > gl) r = mid; else l = mid + 1;
-        }
-        k = l;
+        k = vc_owner(d, gl, [&](uint32_t j) { return P[j].x; });
         const u32x2 rec = P[k];
         cur = rec.y + gl;
         end = rec.y + rec.x;

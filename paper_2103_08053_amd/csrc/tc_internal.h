@@ -104,6 +104,28 @@ __host__ __device__ inline Geometry geometry_fit(uint32_t d, uint32_t S, uint32_
     return h.words <= avail ? h : g;
 }
 
+// Virtual combination (paper Section 4.2): the out-neighbour lists N+(v_0), ..., N+(v_{d-1}) are
+// read as one flattened sequence; incl(k) is the inclusive prefix |N+(v_0)| + ... + |N+(v_k)|.
+// Flattened index i belongs to the first k with incl(k) > i, at position i - incl(k - 1) of that
+// list.  `incl` is any accessor of the prefix (the kernels read it from their records in LDS);
+// d >= 1.  An index at or past incl(d - 1) maps to d - 1.
+template <typename Incl>
+__host__ __device__ inline uint32_t vc_owner(uint32_t d, uint32_t i, Incl incl) {
+    uint32_t l = 0, r = d - 1;
+    while (l < r) {
+        const uint32_t mid = (l + r) >> 1;
+        if (incl(mid) > i) r = mid; else l = mid + 1;
+    }
+    return l;
+}
+
+// The probe's 32-bit list cursor holds byte offsets into col: a lane may step up to 256 bytes past
+// the end of its last list before it moves on, so 32-bit offsets hold while 4 m + 256 < 2^32.  Past
+// that (or when asked), the cursor is a word index with 64-bit addressing.
+__host__ __device__ inline bool wide_list_addressing(uint64_t m_in, bool forced) {
+    return forced || 4ull * m_in + 256ull >= (1ull << 32);
+}
+
 // Largest d whose table fits in `words` 32-bit words (0 if none).
 inline uint32_t capacity(uint32_t words, uint32_t S, uint32_t load_pct, bool pv) {
     const uint32_t lr = load_recip(load_pct);

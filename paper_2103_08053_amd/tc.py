@@ -23,7 +23,7 @@ EXPORTS = [
     "tc_count_scratch_bytes", "tc_graph_count", "tc_graph_info_get", "tc_graph_release",
     "tc_timing_enable", "tc_timing_last", "tc_batch_footprint", "tc_batch_build", "tc_graph_count_each",
     "tc_graph_count_replay", "tc_graph_k", "tc_graph_count_shard", "tc_graph_collisions",
-    "tc_graph_count_simple", "tc_graph_bin_work",
+    "tc_graph_count_simple", "tc_graph_bin_work", "tc_vc_locate", "tc_wide_list_addressing",
 ]
 
 
@@ -136,6 +136,8 @@ def load_library(path: str = LIB_PATH):
         "tc_graph_bin_work": [vp, vp, ctypes.POINTER(u64)],
         "tc_graph_k": [vp, ctypes.POINTER(u32)],
         "tc_timing_last": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+        "tc_vc_locate": [ctypes.POINTER(u32), u32, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)],
+        "tc_wide_list_addressing": [u64, u32, ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -410,6 +412,23 @@ class Batch(Graph):
         vo = torch.from_numpy(voff).to(dev, non_blocking=True)
         eo = torch.from_numpy(eoff).to(dev, non_blocking=True)
         super().__init__(ctx, src, dst, int(voff[-1]), stream=stream, _batch=(len(graphs), vo, eo), sync=sync)
+
+
+def vc_locate(incl_prefix, index: int) -> tuple[int, int]:
+    """(list k, position in it) of flattened index ``index`` under virtual combination, computed by
+    the library's own index-map code on the host (``tc_vc_locate``)."""
+    lib = load_library()
+    arr = (ctypes.c_uint32 * len(incl_prefix))(*[int(x) for x in incl_prefix])
+    k, off = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib.tc_vc_locate(arr, len(incl_prefix), int(index), ctypes.byref(k), ctypes.byref(off)))
+    return k.value, off.value
+
+
+def wide_list_addressing(m_in: int, flags: int = 0) -> bool:
+    """Whether a count over m_in edge samples uses 64-bit list addressing (``tc_wide_list_addressing``)."""
+    w = ctypes.c_int()
+    _check(load_library().tc_wide_list_addressing(int(m_in), int(flags), ctypes.byref(w)))
+    return bool(w.value)
 
 
 _default_ctx = None

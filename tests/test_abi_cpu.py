@@ -3,6 +3,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2103_08053_amd import tc
@@ -85,3 +86,52 @@ def test_no_device_is_reported(monkeypatch):
     assert lib.tc_create(0, None, ctypes.byref(h)) == tc.TC_E_DEVICE
     with pytest.raises(tc.TCError):
         tc.Context(0)
+
+
+def read_fixture(name):
+    """key -> list of ints from a tests/golden text fixture (comment lines start with '#')."""
+    out = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            key, *vals = line.split()
+            out[key] = [int(v) for v in vals]
+    return out
+
+
+def test_virtual_combination_worked_example():
+    """The worked example of Section 4.2, through the index-map code the count kernels run
+    (tc_vc_locate evaluates the same template on the host): neighbours {2,3,4,5,7} with 2-hop list
+    lengths {7,3,2,6,5}; flattened index 11 is the second entry (offset 1) of neighbour 4's list."""
+    fx = read_fixture("paper_vc_example.txt")
+    nbrs, lens = fx["neighbours"], fx["degrees"]
+    incl = list(np.cumsum(lens))
+    assert incl == fx["inclusive_prefix"]
+    k, off = tc.vc_locate(incl, fx["query_index"][0])
+    assert nbrs[k] == fx["owner"][0] and off == fx["local_offset"][0]
+
+
+def test_virtual_combination_map_is_the_concatenation():
+    """Every flattened index maps to the list and position it has in the concatenation of the
+    lists, empty lists included (they own no index); indices past the end are rejected."""
+    for lens in ([7, 3, 2, 6, 5], [1], [0, 0, 4, 0, 1, 0], [5, 0, 0], [64] * 9, [3, 65, 1, 128]):
+        incl = list(np.cumsum(lens))
+        flat = [(k, j) for k, ln in enumerate(lens) for j in range(ln)]
+        assert [tc.vc_locate(incl, i) for i in range(len(flat))] == flat
+        with pytest.raises(tc.TCError):
+            tc.vc_locate(incl, incl[-1])
+    with pytest.raises(tc.TCError):
+        tc.vc_locate([], 0)
+
+
+def test_list_addressing_threshold():
+    """32-bit byte cursors while 4 m_in + 256 < 2^32 (a lane may step 256 bytes past its last list);
+    64-bit addressing from m_in = 2^30 - 64 on, or when forced."""
+    edge = (1 << 30) - 64
+    assert not tc.wide_list_addressing(edge - 1)
+    assert tc.wide_list_addressing(edge)
+    assert tc.wide_list_addressing(1 << 30)
+    assert not tc.wide_list_addressing(0) and not tc.wide_list_addressing(67108864)
+    assert tc.wide_list_addressing(100, flags=tc.TC_F_WIDE_ADDR)
+    for m in (edge - 1, edge):  # the rule itself: the largest byte offset a cursor reaches fits in 32 bits
+        assert (4 * m + 256 < 2**32) == (not tc.wide_list_addressing(m))

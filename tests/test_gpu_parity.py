@@ -212,9 +212,11 @@ def test_graph_info_matches_oracle(ctx):
 
 # ----------------------------------------------------------------------------- full-size workload
 
-def check_full_size(ctx, name, gen, one_shot=True):
+def check_full_size(ctx, name, gen, one_shot=True, live=False):
     """Total, a checksum of the whole per-vertex array and sampled per-vertex
-    counts against values stored by the oracle, plus sum t(x) = 3T."""
+    counts against values stored by the oracle, plus sum t(x) = 3T.  With
+    `live` the oracle also runs here and the whole per-vertex array is
+    compared element by element."""
     data = json.load(open(GOLDEN))
     if name not in data:
         pytest.skip(f"no stored oracle values for {name} (tests/golden/make_expected.py)")
@@ -235,6 +237,13 @@ def check_full_size(ctx, name, gen, one_shot=True):
     ids = np.array(exp["sample_ids"])
     assert (pvn[ids] == np.array(exp["sample_counts"], dtype=np.uint64)).all()
     assert int(pvn.sum()) == 3 * tot
+    if live:
+        say(f"[gpu] {name}: oracle per-vertex run")
+        r = oracle.count(g.n, g.src, g.dst, per_vertex=True)
+        say(f"[gpu] {name}: oracle took {r.t_clean_s + r.t_count_s:.1f} s on {r.threads} threads")
+        assert r.total == tot
+        bad = np.flatnonzero(pvn != r.per_vertex)
+        assert bad.size == 0, (bad[:10], pvn[bad[:10]], r.per_vertex[bad[:10]])
     graph.release()
     del graph, pv
     if one_shot:  # the one-shot entry point the benchmark times agrees
@@ -242,8 +251,9 @@ def check_full_size(ctx, name, gen, one_shot=True):
 
 
 def test_rmat_scale22_full_size(ctx, torch):
-    """The throughput workload (R-MAT scale 22), in the launch configuration the benchmark times."""
-    check_full_size(ctx, "rmat22", W.large_rmat)
+    """The throughput workload (R-MAT scale 22), in the launch configuration the benchmark times;
+    every vertex's count against a live oracle run."""
+    check_full_size(ctx, "rmat22", W.large_rmat, live=True)
 
 
 def test_er_2pow25_full_size(ctx, torch):

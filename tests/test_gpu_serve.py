@@ -1,4 +1,4 @@
-"""Serving loop and autotuner on the GPU: results never change."""
+"""Serving loop and autotuner on the GPU: every answer is the oracle's count."""
 import sys
 
 import numpy as np
@@ -6,6 +6,7 @@ import pytest
 
 import graphgen as gg
 import graphgen.workloads as W
+import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -22,6 +23,7 @@ def test_served_results_equal_alone():
         + [gg.complete(60), gg.torus3d(8)]
     ctx = Context(0)
     alone = [ctx.count(g.src, g.dst, g.n)[0] for g in pool]
+    assert alone == [oracle.count(g.n, g.src, g.dst).total for g in pool]
     arrivals = W.poisson_arrivals(400.0, 0.5, seed=3)
     say(f"[gpu] serving {len(arrivals)} requests")
     pinned = [serve.make_request(i, g.n, g.src, g.dst) for i, g in enumerate(pool)]
@@ -41,8 +43,8 @@ def test_fifo_baseline_results():
     arrivals = np.linspace(0, 0.05, 10)
     reqs = [serve.make_request(i, pool[i % 2].n, pool[i % 2].src, pool[i % 2].dst) for i in range(10)]
     serve.serve_fifo(ctx, reqs, arrivals)
-    alone = [ctx.count(g.src, g.dst, g.n)[0] for g in pool]
-    assert all(r.total == alone[r.rid % 2] for r in reqs)
+    want = [oracle.count(g.n, g.src, g.dst).total for g in pool]
+    assert all(r.total == want[r.rid % 2] for r in reqs)
 
 
 def test_autotune_keeps_counts(tmp_path):
@@ -53,7 +55,12 @@ def test_autotune_keeps_counts(tmp_path):
                            cache_path=str(tmp_path / "t.json"))
     say(f"[gpu] tuned {rep}")
     assert rep["evaluated"] >= 4
-    assert Context(0, p).count(g.src, g.dst, g.n)[0] == Context(0).count(g.src, g.dst, g.n)[0]
+    want = oracle.count(g.n, g.src, g.dst).total
+    assert Context(0, p).count(g.src, g.dst, g.n)[0] == want
+    # every candidate of the space counts exactly (the tuner itself checks each against the default)
+    for knob, vals in space.items():
+        for v in vals:
+            assert Context(0, autotune._with(p, knob, v)).count(g.src, g.dst, g.n)[0] == want, (knob, v)
     p2, rep2 = autotune.tune((g.src, g.dst, g.n), space=space, cache_path=str(tmp_path / "t.json"))
     assert rep2["cached"] and p2 == p
 
@@ -75,8 +82,7 @@ def test_idle_requests_go_direct_and_match():
     batched; every answer equals the graph counted alone."""
     from paper_2103_08053_amd import Context, serve
     pool = [gg.rmat(11, 16, seed=2), gg.barabasi_albert(5000, 6, seed=3), gg.complete(40)]
-    ctx = Context(0)
-    alone = [ctx.count(g.src, g.dst, g.n)[0] for g in pool]
+    alone = [oracle.count(g.n, g.src, g.dst).total for g in pool]
     arrivals = np.concatenate([np.arange(6) * 0.03, 0.25 + np.zeros(12)])  # sparse, then a burst
     pinned = [serve.make_request(i, g.n, g.src, g.dst) for i, g in enumerate(pool)]
     reqs = [serve.Request(i, pinned[i % 3].n, pinned[i % 3].src, pinned[i % 3].dst) for i in range(len(arrivals))]

@@ -89,8 +89,9 @@ def test_serving_summary():
 def test_algorithmic_bytes_formula():
     sys.path.insert(0, ROOT)
     import bench
-    assert bench.algorithmic_bytes(10, 20, 300, False) == 80 + 80 + 320 + 1200 + 8
-    assert bench.algorithmic_bytes(10, 20, 300, True) == 80 + 80 + 320 + 1200 + 8 + 80
+    # 32-bit offsets: 4n (u bounds) + 4m (u lists) + 8m (out-neighbour bounds) + 4 W+ + 8 (+ 8n counts)
+    assert bench.algorithmic_bytes(10, 20, 300, False) == 40 + 80 + 160 + 1200 + 8
+    assert bench.algorithmic_bytes(10, 20, 300, True) == 40 + 80 + 160 + 1200 + 8 + 80
 
 
 def test_bench_refuses_more_than_one_gpu():

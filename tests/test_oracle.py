@@ -223,16 +223,29 @@ def test_out_of_range_rejected():
         oracle.vertex_counts(5, np.array([0], np.uint32), np.array([1], np.uint32), np.array([7], np.uint32))
 
 
-def test_stride_sample_is_a_partition():
-    """Counting only x with x % s == r for every residue r covers each triangle
-    exactly once (by its lowest vertex), so stride 1 equals the full count and
-    the sampled work never exceeds it."""
-    g = gg.rmat(12, 16, seed=8)
+def test_stride_sample_counts_exactly_the_sampled_owners():
+    """stride s counts only the vertices x with x % s == 0: its total is the number of triangles
+    whose (degree, id)-first vertex x is such a vertex, enumerated here in Python from the oriented
+    lists (sum over sampled x and y in N+(x) of |N+(x) & N+(y)|), and its work figures are those
+    vertices' edges and 2-hop lengths.  An inverted or shifted filter fails this."""
+    g = gg.dirty(gg.rmat(11, 16, seed=8), seed=9)
+    deg, dplus, nbr = oracle.oriented(g.n, g.src, g.dst)
+    off = np.concatenate([[0], np.cumsum(dplus.astype(np.int64))])
+    lists = [set(nbr[off[x]:off[x + 1]].tolist()) for x in range(g.n)]
+    owned = np.array([sum(len(lists[x] & lists[y]) for y in lists[x]) for x in range(g.n)], np.int64)
     full = run(g, pv=False)
-    part = oracle.count(g.n, g.src, g.dst, stride=3)
-    assert part.total <= full.total
-    assert part.counted_wedges <= full.wedges_plus
-    assert oracle.count(g.n, g.src, g.dst, stride=1).total == full.total
+    assert owned.sum() == full.total
+    for s in (1, 2, 3, 7):
+        sel = np.arange(g.n) % s == 0
+        r = oracle.count(g.n, g.src, g.dst, stride=s)
+        assert r.total == int(owned[sel].sum()), s
+        assert r.counted_vertices == int(sel.sum())
+        assert r.counted_edges == int(dplus[sel].sum())
+        assert r.counted_wedges == sum(int(dplus[y]) for x in np.flatnonzero(sel) for y in lists[x])
+        assert r.wedges_plus == full.wedges_plus  # W+ is always over the whole graph
+    # the residues other than 0 are not counted: with s = 2 the odd owners' triangles are missing
+    odd = int(owned[np.arange(g.n) % 2 == 1].sum())
+    assert odd > 0 and oracle.count(g.n, g.src, g.dst, stride=2).total == full.total - odd
 
 
 def test_erdos_renyi_expected_triangles():

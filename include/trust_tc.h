@@ -16,7 +16,8 @@
  *   - Memory: every device buffer is owned by the caller.  The library never
  *     allocates or frees device memory; its scratch space comes from a
  *     caller-provided workspace sized by the matching *_bytes query.  Host
- *     memory is allocated only for the opaque handles.
+ *     memory is allocated only for the opaque handles and a context's pinned
+ *     staging buffers (tc_count_graphs).
  *   - Ids: vertex ids are uint32 in [0, n), n <= 2^32 - 1.  Edge samples may
  *     repeat, appear in both directions or be self-loops; all are accepted and
  *     cleaned.  n = 0 or m_in = 0 gives a count of 0.
@@ -266,6 +267,41 @@ tc_status tc_graph_count_replay(tc_context* ctx, tc_graph* g, uint64_t* d_totals
 
 /* Number of graphs (k) of a built graph or batch. */
 tc_status tc_graph_k(const tc_graph* g, uint32_t* k);
+
+/* ---------------------------------------------------------------- many built graphs, one launch
+ * The problem of the paper (Sections 1 and 2.1: the triangle count of each undirected simple graph)
+ * over k graphs that were built independently (tc_graph_build or tc_batch_build handles, resident on
+ * this context's device): ONE persistent count launch serves all of them (plus the large-vertex
+ * launch, a set-up launch before them and, with per-vertex output, one gather launch after).
+ *
+ * tc_count_graphs_bytes: device workspace for any call with at most k handles whose vertex counts
+ * sum to at most n_total and whose handles have at most m_max edge samples each, for graphs built
+ * with the context's current parameters, with per-vertex output (per_vertex != 0: 8 n_total bytes
+ * more) or without.  TC_E_UNSUPPORTED when m_max >= 2^31 or n_total + 5 k >= 2^32.
+ *
+ * tc_count_graphs: graphs[0..k-1] are handles built with identical tc_params (TC_E_INVALID
+ * otherwise; TC_E_UNSUPPORTED for the subwave intra-vertex flags).  d_totals: device uint64 array
+ * with one entry per graph: handle g (a batch handle holds k_g graphs, a single graph 1) writes
+ * entries [t_g, t_g + k_g), t_g = k_0 + ... + k_{g-1}; they are overwritten, not added to.
+ * d_per_vertex: NULL, or a host array of k device pointers, entry g a uint64[n_g] that receives
+ * the triangles through each vertex of handle g (input-id order; may be NULL when n_g = 0).
+ * d_ws: device workspace of ws_bytes (TC_E_NOMEM if smaller than these graphs need); its contents
+ * are clobbered.  Asynchronous on `stream`: the handles' builds must be ordered before it (same
+ * stream, or an event), and the call copies a header and one 80-byte descriptor per handle from
+ * context-owned pinned host memory into the start of d_ws (pinned host buffers are the only memory
+ * a context allocates for itself, apart from the handles).  Calls that share a workspace must be
+ * ordered on one stream.
+ *
+ * tc_count_graphs_replay: the same, but the device launches are captured once into a HIP graph per
+ * (workspace address, per-vertex on or off, tc_params) and replayed after the descriptor upload.
+ * The launches read k, the descriptors and every size from the workspace, so one capture serves
+ * every later call, whatever graphs and k it brings (within the workspace's size). */
+tc_status tc_count_graphs_bytes(const tc_context* ctx, uint32_t k, uint64_t n_total, uint64_t m_max, int per_vertex,
+                                uint64_t* bytes);
+tc_status tc_count_graphs(tc_context* ctx, uint32_t k, tc_graph* const* graphs, uint64_t* d_totals,
+                          uint64_t* const* d_per_vertex, void* d_ws, uint64_t ws_bytes, void* stream);
+tc_status tc_count_graphs_replay(tc_context* ctx, uint32_t k, tc_graph* const* graphs, uint64_t* d_totals,
+                                 uint64_t* const* d_per_vertex, void* d_ws, uint64_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- host-side helpers (no device work)
  * tc_vc_locate: the index map of virtual combination (paper Section 4.2),

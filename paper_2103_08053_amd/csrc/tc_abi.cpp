@@ -23,11 +23,30 @@ struct tc_context {
     bool timing = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // build start/end, count start/end
     bool have_build = false, have_count = false;
-    hipStream_t capture_stream = nullptr;  // for tc_graph_count_replay
+    hipStream_t capture_stream = nullptr;  // for tc_graph_count_replay and tc_count_graphs_replay
     struct Occ {
-        uint32_t hub, sw, S, pv, hk, threads, lds;
+        uint32_t hub, sw, mu, S, pv, hk, threads, lds;
         int per_cu;
     };
+    // tc_count_graphs: pinned host staging of the header and descriptors (a small ring, so an upload
+    // still queued behind earlier work is never overwritten), and launch sequences captured per
+    // (workspace, per-vertex mode, knobs).
+    struct Stage {
+        void* host = nullptr;
+        size_t bytes = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    Stage stage[4];
+    uint32_t stage_next = 0;
+    struct MultiCapture {
+        const void* ws;
+        bool pv;
+        tc_params p;
+        hipGraph_t hg;
+        hipGraphExec_t exec;
+    };
+    std::vector<MultiCapture> mcap;
     std::vector<Occ> occ;  // resident workgroups per CU, by kernel variant and launch shape
 };
 
@@ -52,7 +71,7 @@ namespace {
 using tc::Layout;
 
 constexpr size_t kAlign = 256;
-inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+constexpr size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 tc_status fail(tc_context* c, tc_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 tc_status fail(tc_context* c, tc_status s, const char* fmt, ...) {
@@ -269,19 +288,23 @@ uint32_t launch_lds(const tc_context* ctx, const tc_params& p, bool hub) {
     return hub ? ctx->big_lds_bytes : p.wg_lds_bytes;
 }
 
-tc_status occupancy(tc_context* ctx, const tc_params& p, bool pv, bool hub, int* per_cu) {
+tc_status occupancy(tc_context* ctx, const tc_params& p, bool pv, bool hub, int* per_cu, bool multi = false) {
     const uint32_t threads = launch_threads(p, hub), lds = launch_lds(ctx, p, hub);
-    const uint32_t sw = (!hub && subwave_lanes(p.flags)) ? 1u : 0u;
+    const uint32_t sw = (!hub && !multi && subwave_lanes(p.flags)) ? 1u : 0u;
+    const uint32_t mu = multi ? 1u : 0u;
     for (const auto& o : ctx->occ)
-        if (o.hub == (uint32_t)hub && o.sw == sw && o.S == p.slots_per_bucket && o.pv == (uint32_t)pv &&
-            o.hk == p.hash_kind && o.threads == threads && o.lds == lds) {
+        if (o.hub == (uint32_t)hub && o.sw == sw && o.mu == mu && o.S == p.slots_per_bucket &&
+            o.pv == (uint32_t)pv && o.hk == p.hash_kind && o.threads == threads && o.lds == lds) {
             *per_cu = o.per_cu;
             return TC_OK;
         }
     int q = 0;
-    HIP_TRY(ctx, tc::count_kernel_info(hub, sw != 0, p.slots_per_bucket, pv, p.hash_kind, threads, lds, &q));
+    if (multi)
+        HIP_TRY(ctx, tc::count_kernel_info_multi(hub, p.slots_per_bucket, pv, p.hash_kind, threads, lds, &q));
+    else
+        HIP_TRY(ctx, tc::count_kernel_info(hub, sw != 0, p.slots_per_bucket, pv, p.hash_kind, threads, lds, &q));
     if (q < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, lds);
-    ctx->occ.push_back({(uint32_t)hub, sw, p.slots_per_bucket, (uint32_t)pv, p.hash_kind, threads, lds, q});
+    ctx->occ.push_back({(uint32_t)hub, sw, mu, p.slots_per_bucket, (uint32_t)pv, p.hash_kind, threads, lds, q});
     *per_cu = q;
     return TC_OK;
 }
@@ -356,6 +379,77 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
 
 tc_status count_one_shot(tc_context* ctx, uint32_t n, uint64_t m_in, const uint32_t* d_src, const uint32_t* d_dst,
                          uint64_t* d_per_vertex, void* d_ws, const Layout& L, hipStream_t st, uint64_t* h_total);
+
+// ---------------------------------------------------------------- several built graphs, one launch sequence
+
+// Workspace of a multi-graph count: header | queue heads | descriptors | per-bin fetch prefixes |
+// per-vertex staging | global-memory tables.  The header and the heads sit at fixed offsets (the
+// kernels are given those two addresses; everything else is read from the header); every other
+// region grows with (k, n_total, hub_words), so the sizes of any call within a query's bounds fit
+// the query's answer.
+constexpr size_t kMultiHeads = align_up(sizeof(tc::MultiHeader));
+struct MultiLayout {
+    size_t desc, pre, tv, hub, bytes;
+    uint32_t hub_wgs;
+};
+
+MultiLayout multi_layout(const tc_context* ctx, const tc_params& p, uint32_t k, uint64_t n_total, bool pv,
+                         uint64_t hub_words) {
+    MultiLayout M{};
+    size_t o = align_up(kMultiHeads + 4 * (size_t)tc::kHeadWords);
+    M.desc = o;  o = align_up(o + sizeof(tc::MultiDesc) * (size_t)k);
+    M.pre = o;   o = align_up(o + 4 * (size_t)tc::kBins * ((size_t)k + 1));
+    M.tv = o;    o = align_up(o + (pv ? 8 * (size_t)n_total : 0));
+    const uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)std::max(1, ctx ? ctx->cu_count : 1);
+    M.hub_wgs = std::min<uint32_t>(tc::kHubWgs, std::max<uint32_t>(1, grid));
+    M.hub = o;   o = align_up(o + 4 * (size_t)hub_words * M.hub_wgs);
+    M.bytes = o;
+    return M;
+}
+
+// Words of one global-memory table region for a graph of n vertices and m_in samples.
+uint64_t hub_words_for(const tc_params& p, uint32_t n, uint64_t m_in) {
+    if (n == 0 || m_in == 0) return 0;
+    return tc::geometry(dplus_bound(n, m_in), p.slots_per_bucket, tc::load_recip(p.load_factor_pct), true).words;
+}
+
+// The launches of a multi-graph count (clears and prefixes, large-vertex kernel, main kernel,
+// per-vertex gather), every size read from the header at hdr.  `record`: timing events (not while
+// capturing).  Launch shapes come from occupancy queries resolved beforehand.
+tc_status multi_launches(tc_context* ctx, const tc_params& p, bool pv, tc::MultiHeader* hdr, uint32_t hub_wgs,
+                         hipStream_t s, bool record) {
+    int per_cu = 0, per_cu_hub = 0;
+    if (tc_status st = occupancy(ctx, p, pv, false, &per_cu, true)) return st;
+    if (tc_status st = occupancy(ctx, p, pv, true, &per_cu_hub, true)) return st;
+    const uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu * ctx->cu_count);
+    const uint32_t grid_hub = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu_hub * ctx->cu_count);
+    tc::CountArgs a{};
+    a.multi = hdr;
+    a.heads = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(hdr) + kMultiHeads);
+    a.slice_words = slice_words(p);
+    a.lrecip = tc::load_recip(p.load_factor_pct);
+    a.chunk = p.light_chunk;
+    a.pack_region = pack_region(p);
+    a.subwave = 0;
+    a.shard = 0;
+    a.shards = 1;
+    a.hub_wgs = std::min(hub_wgs, grid_hub);
+    HIP_TRY(ctx, tc::multi_prepare(hdr, ctx->cu_count, s));
+    const bool rec = record && ctx->timing;
+    if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
+    a.table_words = launch_lds(ctx, p, true) / 4;
+    HIP_TRY(ctx, tc::count_launch_multi(true, p.slots_per_bucket, pv, p.hash_kind, grid_hub, launch_threads(p, true),
+                                        launch_lds(ctx, p, true), a, s));
+    a.table_words = p.wg_lds_bytes / 4;
+    HIP_TRY(ctx, tc::count_launch_multi(false, p.slots_per_bucket, pv, p.hash_kind, grid, launch_threads(p, false),
+                                        p.wg_lds_bytes, a, s));
+    if (rec) {
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
+        ctx->have_count = true;
+    }
+    if (pv) HIP_TRY(ctx, tc::multi_gather(hdr, ctx->cu_count, s));
+    return TC_OK;
+}
 
 void drop_capture(tc_graph* g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -436,6 +530,17 @@ tc_status tc_destroy(tc_context* ctx) {
     if (!ctx) return TC_OK;
     for (hipEvent_t& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& c : ctx->mcap) {
+        if (c.exec) (void)hipGraphExecDestroy(c.exec);
+        if (c.hg) (void)hipGraphDestroy(c.hg);
+    }
+    for (auto& st : ctx->stage) {
+        if (st.ev) {
+            (void)hipEventSynchronize(st.ev);
+            (void)hipEventDestroy(st.ev);
+        }
+        if (st.host) (void)hipHostFree(st.host);
+    }
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
     return TC_OK;
@@ -821,6 +926,169 @@ tc_status tc_graph_count_replay(tc_context* ctx, tc_graph* g, uint64_t* d_totals
     }
     HIP_TRY(ctx, hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
     return TC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// A pinned staging slot of at least `bytes`, free to overwrite (its last upload has been read).
+tc_status staging(tc_context* ctx, size_t bytes, tc_context::Stage** out) {
+    tc_context::Stage& st = ctx->stage[ctx->stage_next];
+    ctx->stage_next = (ctx->stage_next + 1) % (uint32_t)(sizeof(ctx->stage) / sizeof(ctx->stage[0]));
+    if (!st.ev) HIP_TRY(ctx, hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
+    if (st.pending) {
+        HIP_TRY(ctx, hipEventSynchronize(st.ev));
+        st.pending = false;
+    }
+    if (st.bytes < bytes) {
+        if (st.host) HIP_TRY(ctx, hipHostFree(st.host));
+        st.host = nullptr;
+        st.bytes = 0;
+        size_t cap = 65536;
+        while (cap < bytes) cap *= 2;
+        HIP_TRY(ctx, hipHostMalloc(&st.host, cap, hipHostMallocDefault));
+        st.bytes = cap;
+    }
+    *out = &st;
+    return TC_OK;
+}
+
+// tc_count_graphs and its replayed form: checks, the header and descriptors (one upload into the
+// workspace), then the launches, direct or from the capture for (workspace, per-vertex mode, knobs).
+tc_status count_graphs(tc_context* ctx, uint32_t k, tc_graph* const* graphs, uint64_t* d_totals,
+                       uint64_t* const* d_per_vertex, void* d_ws, uint64_t ws_bytes, hipStream_t s, bool replay) {
+    if (!ctx) return TC_E_INVALID;
+    ctx->err.clear();
+    if (k == 0 || !graphs || !d_totals) return fail(ctx, TC_E_INVALID, "k >= 1 graphs and a totals array are required");
+    for (uint32_t g = 0; g < k; ++g) {
+        if (!graphs[g]) return fail(ctx, TC_E_INVALID, "graph %u is null", g);
+        if (graphs[g]->ctx->device != ctx->device) return fail(ctx, TC_E_INVALID, "graph %u is on another device", g);
+        if (std::memcmp(&graphs[g]->p, &graphs[0]->p, sizeof(tc_params)) != 0)
+            return fail(ctx, TC_E_INVALID, "graph %u was built with other parameters than graph 0", g);
+    }
+    const tc_params p = graphs[0]->p;
+    if (subwave_lanes(p.flags))
+        return fail(ctx, TC_E_UNSUPPORTED, "subwave intra-vertex modes count one graph at a time");
+    const bool pv = d_per_vertex != nullptr;
+    uint64_t n_total = 0, n_totals = 0, hub_words = 0;
+    for (uint32_t g = 0; g < k; ++g) {
+        const tc_graph* G = graphs[g];
+        if (pv && G->n && !d_per_vertex[g]) return fail(ctx, TC_E_INVALID, "per-vertex output %u is null", g);
+        n_total += G->n;
+        n_totals += G->k;
+        hub_words = std::max<uint64_t>(hub_words, hub_words_for(p, G->n, G->m_in));
+    }
+    if (n_total + (uint64_t)tc::kBins * k >= (1ull << 32))
+        return fail(ctx, TC_E_UNSUPPORTED, "%llu vertices in one call (limit 2^32 - 1 - 5 k)",
+                    (unsigned long long)n_total);
+    const MultiLayout M = multi_layout(ctx, p, k, n_total, pv, hub_words);
+    if (!d_ws || ws_bytes < M.bytes)
+        return fail(ctx, TC_E_NOMEM, "workspace %llu bytes < %llu needed", (unsigned long long)ws_bytes,
+                    (unsigned long long)M.bytes);
+    if (tc_status st = use_device(ctx)) return st;
+
+    // Header and descriptors, written to pinned memory and uploaded with one copy.
+    const size_t up = M.desc + sizeof(tc::MultiDesc) * (size_t)k;
+    tc_context::Stage* st = nullptr;
+    if (tc_status e = staging(ctx, up, &st)) return e;
+    char* ws = static_cast<char*>(d_ws);
+    char* h = static_cast<char*>(st->host);
+    std::memset(h, 0, M.desc);
+    tc::MultiHeader* H = reinterpret_cast<tc::MultiHeader*>(h);
+    H->k = k;
+    H->pv = pv ? 1u : 0u;
+    H->n_total = n_total;
+    H->n_totals = n_totals;
+    H->totals = reinterpret_cast<unsigned long long*>(d_totals);
+    H->desc = reinterpret_cast<const tc::MultiDesc*>(ws + M.desc);
+    H->pre = reinterpret_cast<uint32_t*>(ws + M.pre);
+    H->tv = reinterpret_cast<unsigned long long*>(ws + M.tv);
+    H->heads = reinterpret_cast<uint32_t*>(ws + kMultiHeads);
+    H->hub = reinterpret_cast<uint32_t*>(ws + M.hub);
+    H->hub_words = hub_words;
+    const uint32_t pf[tc::kBins] = {1u, 1u, 1u, p.light_chunk, 4u * p.light_chunk};
+    for (uint32_t b = 0; b < tc::kBins; ++b) H->per_fetch[b] = pf[b];
+    tc::MultiDesc* D = reinterpret_cast<tc::MultiDesc*>(h + M.desc);
+    uint64_t tv0 = 0, t0 = 0;
+    for (uint32_t g = 0; g < k; ++g) {
+        const tc_graph* G = graphs[g];
+        tc::MultiDesc& d = D[g];
+        std::memset(&d, 0, sizeof(d));
+        d.meta = G->empty ? nullptr : G->dev.meta;
+        d.off = G->dev.off32;
+        d.col = G->dev.col;
+        d.items = G->dev.items;
+        d.rank = G->dev.rank;
+        d.gid = G->dev.gid;
+        d.totals = reinterpret_cast<unsigned long long*>(d_totals + t0);
+        d.out = pv ? reinterpret_cast<unsigned long long*>(d_per_vertex[g]) : nullptr;
+        d.tv0 = tv0;
+        d.n = G->n;
+        d.wide = tc::wide_list_addressing(G->m_in, (p.flags & TC_F_WIDE_ADDR) != 0) ? 1u : 0u;
+        tv0 += G->n;
+        t0 += G->k;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ws, h, up, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipEventRecord(st->ev, s));
+    st->pending = true;
+
+    tc::MultiHeader* hdr = reinterpret_cast<tc::MultiHeader*>(ws);
+    if (!replay) return multi_launches(ctx, p, pv, hdr, M.hub_wgs, s, true);
+
+    tc_context::MultiCapture* cap = nullptr;
+    for (auto& c : ctx->mcap)
+        if (c.ws == d_ws && c.pv == pv && std::memcmp(&c.p, &p, sizeof(p)) == 0) cap = &c;
+    if (!cap) {
+        if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        int q = 0;  // launch shapes resolved before capture (no attribute calls while capturing)
+        if (tc_status e = occupancy(ctx, p, pv, false, &q, true)) return e;
+        if (tc_status e = occupancy(ctx, p, pv, true, &q, true)) return e;
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        tc_status e = multi_launches(ctx, p, pv, hdr, M.hub_wgs, ctx->capture_stream, false);
+        hipGraph_t hg = nullptr;
+        hipError_t he = hipStreamEndCapture(ctx->capture_stream, &hg);
+        if (e != TC_OK) {
+            if (hg) (void)hipGraphDestroy(hg);
+            return e;
+        }
+        if (he != hipSuccess) return hip_fail(ctx, he, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        he = hipGraphInstantiate(&exec, hg, nullptr, nullptr, 0);
+        if (he != hipSuccess) {
+            (void)hipGraphDestroy(hg);
+            return hip_fail(ctx, he, "hipGraphInstantiate");
+        }
+        ctx->mcap.push_back({d_ws, pv, p, hg, exec});
+        cap = &ctx->mcap.back();
+    }
+    HIP_TRY(ctx, hipGraphLaunch(cap->exec, s));
+    return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tc_status tc_count_graphs_bytes(const tc_context* ctx, uint32_t k, uint64_t n_total, uint64_t m_max, int per_vertex,
+                                uint64_t* bytes) {
+    if (!ctx || !bytes || k == 0) return TC_E_INVALID;
+    if (m_max >= (1ull << 31) || n_total + (uint64_t)tc::kBins * k >= (1ull << 32)) return TC_E_UNSUPPORTED;
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(n_total, 0xFFFFFFFFull);
+    *bytes = multi_layout(ctx, ctx->p, k, n_total, per_vertex != 0, hub_words_for(ctx->p, nb, m_max)).bytes;
+    return TC_OK;
+}
+
+tc_status tc_count_graphs(tc_context* ctx, uint32_t k, tc_graph* const* graphs, uint64_t* d_totals,
+                          uint64_t* const* d_per_vertex, void* d_ws, uint64_t ws_bytes, void* stream) {
+    return count_graphs(ctx, k, graphs, d_totals, d_per_vertex, d_ws, ws_bytes, static_cast<hipStream_t>(stream),
+                        false);
+}
+
+tc_status tc_count_graphs_replay(tc_context* ctx, uint32_t k, tc_graph* const* graphs, uint64_t* d_totals,
+                                 uint64_t* const* d_per_vertex, void* d_ws, uint64_t ws_bytes, void* stream) {
+    return count_graphs(ctx, k, graphs, d_totals, d_per_vertex, d_ws, ws_bytes, static_cast<hipStream_t>(stream),
+                        true);
 }
 
 }  // extern "C"

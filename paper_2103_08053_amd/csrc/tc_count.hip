@@ -43,6 +43,8 @@
 // element is the triangle's w) and a register tally for v_k (added to an LDS
 // tally when the lane leaves v_k's list); after the probe, u's hits and the
 // non-zero tallies go to the per-vertex array with one global atomic each.
+#include <type_traits>
+
 #include "tc_internal.h"
 #include "tc_wave.h"
 
@@ -716,6 +718,58 @@ __device__ __forceinline__ bool in_shard(const CountArgs& a, uint32_t u) {
     return a.shards <= 1 || u % a.shards == a.shard;
 }
 
+// Several graphs in one launch (a.multi): the handle whose fetches of a bin hold the launch-wide
+// fetch c is the last g < k with pre[g] <= c (pre: exclusive prefix over the handles of the bin's
+// fetches, pre[0] = 0 <= c < pre[k]; a handle without fetches repeats its successor's value and is
+// passed over).  A 64-way search by the whole wavefront, one round per factor of 64 in k.
+__device__ __forceinline__ uint32_t find_graph(const uint32_t* pre, uint32_t k, uint32_t c, int lane) {
+    uint32_t lo = 0, hi = k;  // pre[lo] <= c, and hi == k or pre[hi] > c
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + 63) / 64;
+        const uint32_t p = lo + (uint32_t)lane * step;
+        const unsigned long long ok = __ballot(p < hi && pre[p] <= c);  // lane 0: pre[lo] <= c
+        lo += (uint32_t)(63 - __builtin_clzll(ok)) * step;
+        hi = (lo + step < hi) ? lo + step : hi;
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        hi = __builtin_amdgcn_readfirstlane(hi);
+    }
+    return lo;
+}
+
+// The launch-wide arguments with the per-graph fields of handle d.
+__device__ __forceinline__ CountArgs graph_view(const CountArgs& a, const MultiDesc& d) {
+    CountArgs v = a;
+    v.meta = d.meta;
+    v.off = d.off;
+    v.col = d.col;
+    v.items = d.items;
+    v.gid = d.gid;
+    v.totals = d.totals;
+    v.total = d.totals;
+    v.tv = a.multi->tv + d.tv0;
+    v.wide = d.wide;
+    return v;
+}
+
+// First item of bin `bin` in a graph's item list (the bins are stored one after another).
+__device__ __forceinline__ uint32_t bin_base(const GraphMeta* m, uint32_t bin) {
+    uint32_t b = 0;
+    for (uint32_t i = 0; i < bin; ++i) b += m->bins[i];
+    return b;
+}
+
+// Wavefront total of a multi-graph launch: hits of single graphs accumulate in `acc` while they
+// belong to the same graph and go to that graph's total when the wavefront moves to another one.
+struct AccSink {
+    unsigned long long* dst = nullptr;
+    __device__ __forceinline__ void to(unsigned long long* next, unsigned long long& acc, int lane) {
+        if (next == dst) return;
+        if (acc && dst && lane == 0) atomicAdd(dst, acc);
+        acc = 0;
+        dst = next;
+    }
+};
+
 template <int S, bool PV, int HK, bool DEFER, bool SW = false>
 __device__ __forceinline__ void process_wg(const CountArgs& a, uint32_t u, uint32_t* tbl, uint64_t avail, int tid,
                                            int wave, int nw, int lane, uint32_t* s_wsum, unsigned long long& acc,
@@ -750,7 +804,7 @@ __device__ __forceinline__ void add_workgroup_total(const CountArgs& a, unsigned
 // workgroup per CU and the whole LDS: bin 1 tables fill the workgroup's LDS;
 // bin 0 tables (too large for any LDS) live in global memory, one region per
 // participating workgroup (the first hub_wgs workgroups).
-template <int S, bool PV, int HK>
+template <int S, bool PV, int HK, bool MULTI>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) tc_hub_kernel(CountArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t s_wsum[kMaxWaves];
@@ -758,11 +812,36 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     unsigned long long acc = 0;
-    const uint32_t n_hub = a.meta->bins[0], n_big = a.meta->bins[1];
+    AccSink sink;
+    uint32_t n_hub, n_big;
+    if constexpr (MULTI) {
+        n_hub = a.multi->items_tot[0];
+        n_big = a.multi->items_tot[1];
+    } else {
+        n_hub = a.meta->bins[0];
+        n_big = a.meta->bins[1];
+    }
     if (n_hub + n_big == 0) return;
+    // Item j of bin `bin` (launch-wide index in multi-graph mode) with its graph's arguments.
+    auto run = [&](uint32_t bin, uint32_t j, uint32_t* tbl, uint64_t avail, uint32_t part, uint32_t parts, auto wg) {
+        if constexpr (MULTI) {
+            const MultiHeader* H = a.multi;
+            const uint32_t* pre = H->pre + (size_t)bin * (H->k + 1);
+            const uint32_t g = find_graph(pre, H->k, j, lane);
+            const MultiDesc& d = H->desc[g];
+            const CountArgs v = graph_view(a, d);
+            sink.to(d.totals, acc, lane);
+            process_wg<S, PV, HK, decltype(wg)::value>(v, d.items[bin_base(d.meta, bin) + j - pre[g]], tbl, avail, tid,
+                                                       wave, nw, lane, s_wsum, acc, part, parts);
+        } else {
+            process_wg<S, PV, HK, decltype(wg)::value>(a, a.items[(bin ? n_hub : 0u) + j], tbl, avail, tid, wave, nw,
+                                                       lane, s_wsum, acc, part, parts);
+        }
+    };
 
     if (blockIdx.x < a.hub_wgs && n_hub) {
-        uint32_t* gt = a.hub_scratch + (size_t)blockIdx.x * a.hub_words;
+        const unsigned long long hub_words = MULTI ? a.multi->hub_words : a.hub_words;
+        uint32_t* gt = (MULTI ? a.multi->hub : a.hub_scratch) + (size_t)blockIdx.x * hub_words;
         const uint32_t parts = parts_for(n_hub, a.hub_wgs);
         for (;;) {
             if (tid == 0) s_item = atomicAdd(&a.heads[0 * kHeadStride], 1u);
@@ -770,8 +849,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             const uint32_t t = s_item;
             __syncthreads();
             if (t >= n_hub * parts) break;
-            process_wg<S, PV, HK, false>(a, a.items[t / parts], gt, a.hub_words, tid, wave, nw, lane, s_wsum, acc,
-                                         t % parts, parts);
+            run(0u, t / parts, gt, hub_words, t % parts, parts, std::false_type{});
         }
     }
     if (n_big) {
@@ -782,15 +860,16 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             const uint32_t t = s_item;
             __syncthreads();
             if (t >= n_big * parts) break;
-            process_wg<S, PV, HK, true>(a, a.items[n_hub + t / parts], lds, a.table_words, tid, wave, nw, lane, s_wsum,
-                                        acc, t % parts, parts);
+            run(1u, t / parts, lds, a.table_words, t % parts, parts, std::true_type{});
         }
     }
-    add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);
+    if constexpr (MULTI) sink.to(nullptr, acc, lane);
+    else add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);
 }
 
-// Everything else (bins 2 and 3): a persistent grid filling the GPU.  SW: subwave probe assignment.
-template <int S, bool PV, int HK, bool SW>
+// Everything else (bins 2-4): a persistent grid filling the GPU.  SW: subwave probe assignment;
+// MULTI: the graphs come from a.multi.
+template <int S, bool PV, int HK, bool SW, bool MULTI>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) tc_count_kernel(CountArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ uint32_t s_wsum[kMaxWaves];
@@ -798,8 +877,19 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     unsigned long long acc = 0;
-    const uint32_t n_before = a.meta->bins[0] + a.meta->bins[1], n_wg = a.meta->bins[2], n_wave = a.meta->bins[3];
-    const uint32_t n_pack = a.meta->bins[4];
+    AccSink sink;
+    uint32_t n_before, n_wg, n_wave, n_pack;
+    if constexpr (MULTI) {
+        n_before = 0;  // items are found per graph
+        n_wg = a.multi->items_tot[2];
+        n_wave = a.multi->items_tot[3];
+        n_pack = a.multi->items_tot[4];
+    } else {
+        n_before = a.meta->bins[0] + a.meta->bins[1];
+        n_wg = a.meta->bins[2];
+        n_wave = a.meta->bins[3];
+        n_pack = a.meta->bins[4];
+    }
 
     // Workgroup bin: the table fills the workgroup's LDS.
     if (n_wg) {
@@ -809,8 +899,19 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             const uint32_t j = s_item;
             __syncthreads();
             if (j >= n_wg) break;
-            process_wg<S, PV, HK, true, SW>(a, a.items[n_before + j], lds, a.table_words, tid, wave, nw, lane,
-                                            s_wsum, acc);
+            if constexpr (MULTI) {
+                const MultiHeader* H = a.multi;
+                const uint32_t* pre = H->pre + 2u * (H->k + 1);
+                const uint32_t g = find_graph(pre, H->k, j, lane);
+                const MultiDesc& d = H->desc[g];
+                const CountArgs v = graph_view(a, d);
+                sink.to(d.totals, acc, lane);
+                process_wg<S, PV, HK, true, SW>(v, d.items[bin_base(d.meta, 2) + j - pre[g]], lds, a.table_words, tid,
+                                                wave, nw, lane, s_wsum, acc);
+            } else {
+                process_wg<S, PV, HK, true, SW>(a, a.items[n_before + j], lds, a.table_words, tid, wave, nw, lane,
+                                                s_wsum, acc);
+            }
         }
     }
     // Wavefront bins: each wavefront owns a slice of the LDS and takes `per_fetch` vertices at a time.
@@ -819,10 +920,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     // the fetch atomics of a launch with millions of light vertices over kWaveQueues addresses.  A
     // wavefront starts on sub-queue blockIdx % kWaveQueues (one per XCD with round-robin dispatch),
     // moves on when its sub-queue is drained, and requests its next chunk before working on the
-    // current one.  `work(j0, j1)` processes items [j0, j1) of the bin.
+    // current one.  `work(args, base, j0, j1)` processes items base + [j0, j1) of the bin with the
+    // arguments of their graph (in multi-graph mode a chunk never spans two graphs).
     uint32_t* slice = lds + (size_t)wave * a.slice_words;
-    auto drain = [&](uint32_t n_bin, uint32_t per_fetch, uint32_t head0, auto&& work) {
-        const uint32_t nchunks = (n_bin + per_fetch - 1) / per_fetch;
+    auto drain = [&](uint32_t bin, uint32_t n_bin, uint32_t base1, uint32_t per_fetch, uint32_t head0,
+                     auto&& work) {
+        const uint32_t nchunks = MULTI ? a.multi->fetch_tot[bin] : (n_bin + per_fetch - 1) / per_fetch;
         uint32_t q = blockIdx.x % kWaveQueues, drained = 0;
         auto request = [&]() -> uint32_t {
             uint32_t c = 0;
@@ -842,80 +945,88 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         uint32_t cur = settle(request());
         while (cur < nchunks) {
             const uint32_t ticket = request();  // next chunk, settled after this one
-            const uint32_t j0 = cur * per_fetch;
-            work(j0, (j0 + per_fetch < n_bin) ? j0 + per_fetch : n_bin);
+            if constexpr (MULTI) {
+                const MultiHeader* H = a.multi;
+                const uint32_t* pre = H->pre + (size_t)bin * (H->k + 1);
+                const uint32_t g = find_graph(pre, H->k, cur, lane);
+                const MultiDesc& d = H->desc[g];
+                const uint32_t nb = d.meta->bins[bin];
+                const uint32_t j0 = (cur - pre[g]) * per_fetch;
+                sink.to(d.totals, acc, lane);
+                work(graph_view(a, d), bin_base(d.meta, bin), j0, (j0 + per_fetch < nb) ? j0 + per_fetch : nb);
+            } else {
+                const uint32_t j0 = cur * per_fetch;
+                work(a, base1, j0, (j0 + per_fetch < n_bin) ? j0 + per_fetch : n_bin);
+            }
             cur = settle(ticket);
         }
     };
     // Bin 3: one vertex per wavefront.
-    {
-        const uint32_t wbase = n_before + n_wg;
-        drain(n_wave, a.chunk, 3u, [&](uint32_t j0, uint32_t j1) {
-            // The vertices of a fetch and their list bounds are loaded by the wavefront at once
-            // (lane i holds the i-th), so each vertex starts without two dependent loads.
-            for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
-                const uint32_t cnt = (j1 - b0 < 64u) ? j1 - b0 : 64u;
-                uint32_t vu = 0, vb = 0, vd = 0;  // offsets stay below 2^31 (m < 2^31)
-                if ((uint32_t)lane < cnt) {
-                    vu = a.items[wbase + b0 + lane];
-                    vb = (uint32_t)a.off[vu];
-                    vd = (uint32_t)a.off[vu + 1] - vb;
+    drain(3u, n_wave, n_before + n_wg, a.chunk, 3u, [&](const CountArgs& v, uint32_t base, uint32_t j0, uint32_t j1) {
+        // The vertices of a fetch and their list bounds are loaded by the wavefront at once
+        // (lane i holds the i-th), so each vertex starts without two dependent loads.
+        for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
+            const uint32_t cnt = (j1 - b0 < 64u) ? j1 - b0 : 64u;
+            uint32_t vu = 0, vb = 0, vd = 0;  // offsets stay below 2^31 (m < 2^31)
+            if ((uint32_t)lane < cnt) {
+                vu = v.items[base + b0 + lane];
+                vb = (uint32_t)v.off[vu];
+                vd = (uint32_t)v.off[vu + 1] - vb;
+            }
+            // Two-stage prefetch for lists of at most 64: the next vertex's list is loaded while
+            // this one's table is built, and its elements' list bounds while this one is probed.
+            uint32_t xw = 0, xo = 0, xl = 0;
+            auto prime = [&](uint32_t i0) {  // vertex i0's list element and its bounds, loaded now
+                const int64_t beg0 = (int64_t)__builtin_amdgcn_readlane(vb, i0);
+                const uint32_t d0 = __builtin_amdgcn_readlane(vd, i0);
+                xw = xo = xl = 0;
+                if (d0 <= 64u && (uint32_t)lane < d0) {
+                    xw = v.col[beg0 + lane];
+                    xo = (uint32_t)v.off[xw];
+                    xl = (uint32_t)v.off[xw + 1] - xo;
                 }
-                // Two-stage prefetch for lists of at most 64: the next vertex's list is loaded while
-                // this one's table is built, and its elements' list bounds while this one is probed.
-                uint32_t xw = 0, xo = 0, xl = 0;
-                auto prime = [&](uint32_t i0) {  // vertex i0's list element and its bounds, loaded now
-                    const int64_t beg0 = (int64_t)__builtin_amdgcn_readlane(vb, i0);
-                    const uint32_t d0 = __builtin_amdgcn_readlane(vd, i0);
-                    xw = xo = xl = 0;
-                    if (d0 <= 64u && (uint32_t)lane < d0) {
-                        xw = a.col[beg0 + lane];
-                        xo = (uint32_t)a.off[xw];
-                        xl = (uint32_t)a.off[xw + 1] - xo;
+            };
+            prime(0);
+            for (uint32_t i = 0; i < cnt; ++i) {
+                const uint32_t u = __builtin_amdgcn_readlane(vu, i);
+                const int64_t beg = (int64_t)__builtin_amdgcn_readlane(vb, i);
+                const uint32_t d = __builtin_amdgcn_readlane(vd, i);
+                const uint32_t inext = i + 1 < cnt ? i + 1 : i;
+                const int64_t beg_n = (int64_t)__builtin_amdgcn_readlane(vb, inext);
+                const uint32_t d_n = i + 1 < cnt ? __builtin_amdgcn_readlane(vd, inext) : 0u;
+                const bool pre_n = d_n <= 64u && (uint32_t)lane < d_n;
+                uint32_t nw = 0, no = 0, nl = 0;
+                if (pre_n) nw = v.col[beg_n + lane];
+                auto mid = [&]() {
+                    if (pre_n) {
+                        no = (uint32_t)v.off[nw];
+                        nl = (uint32_t)v.off[nw + 1] - no;
                     }
                 };
-                prime(0);
-                for (uint32_t i = 0; i < cnt; ++i) {
-                    const uint32_t u = __builtin_amdgcn_readlane(vu, i);
-                    const int64_t beg = (int64_t)__builtin_amdgcn_readlane(vb, i);
-                    const uint32_t d = __builtin_amdgcn_readlane(vd, i);
-                    const uint32_t inext = i + 1 < cnt ? i + 1 : i;
-                    const int64_t beg_n = (int64_t)__builtin_amdgcn_readlane(vb, inext);
-                    const uint32_t d_n = i + 1 < cnt ? __builtin_amdgcn_readlane(vd, inext) : 0u;
-                    const bool pre_n = d_n <= 64u && (uint32_t)lane < d_n;
-                    uint32_t nw = 0, no = 0, nl = 0;
-                    if (pre_n) nw = a.col[beg_n + lane];
-                    auto mid = [&]() {
-                        if (pre_n) {
-                            no = (uint32_t)a.off[nw];
-                            nl = (uint32_t)a.off[nw + 1] - no;
-                        }
-                    };
-                    if (in_shard(a, u))
-                        process<S, PV, HK, false, true, decltype(mid), SW>(a, u, beg, d, slice, a.slice_words, lane,
-                                                                           64, 0, 1, lane, nullptr, acc, d <= 64u, xw,
-                                                                           xo, xl, mid);
-                    else
-                        mid();
-                    xw = nw;
-                    xo = no;
-                    xl = nl;
-                }
+                if (in_shard(v, u))
+                    process<S, PV, HK, false, true, decltype(mid), SW>(v, u, beg, d, slice, a.slice_words, lane,
+                                                                       64, 0, 1, lane, nullptr, acc, d <= 64u, xw,
+                                                                       xo, xl, mid);
+                else
+                    mid();
+                xw = nw;
+                xo = no;
+                xl = nl;
             }
-        });
-    }
+        }
+    });
     // Bin 4: light vertices (out-degree <= 32, small collective degree) packed several to a
     // wavefront: 4 x 16 lanes when the next 3 or 4 have out-degree <= 16, else 2 x 32 lanes.
     if constexpr (!SW) {
-        const uint32_t pbase = n_before + n_wg + n_wave;
-        drain(n_pack, 4u * a.chunk, 3u + kWaveQueues, [&](uint32_t j0, uint32_t j1) {
+        drain(4u, n_pack, n_before + n_wg + n_wave, 4u * a.chunk, 3u + kWaveQueues,
+              [&](const CountArgs& v, uint32_t base, uint32_t j0, uint32_t j1) {
             for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
                 const uint32_t cnt = (j1 - b0 < 64u) ? j1 - b0 : 64u;
                 uint32_t vu = 0, vb = 0, vd = 0;
                 if ((uint32_t)lane < cnt) {
-                    vu = a.items[pbase + b0 + lane];
-                    vb = (uint32_t)a.off[vu];
-                    vd = (uint32_t)a.off[vu + 1] - vb;
+                    vu = v.items[base + b0 + lane];
+                    vb = (uint32_t)v.off[vu];
+                    vd = (uint32_t)v.off[vu + 1] - vb;
                 }
                 for (uint32_t i = 0; i < cnt;) {
                     uint32_t n16 = 0;
@@ -928,52 +1039,52 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                     const uint32_t ug = (uint32_t)__shfl((int)vu, src, 64);
                     const uint32_t bg = (uint32_t)__shfl((int)vb, src, 64);
                     const uint32_t dg = (uint32_t)__shfl((int)vd, src, 64);
-                    const bool has = gi < np && in_shard(a, ug);
+                    const bool has = gi < np && in_shard(v, ug);
                     if (use16)
-                        process_packed<S, PV, HK, 16>(a, ug, bg, dg, has, slice, a.pack_region, lane, acc);
+                        process_packed<S, PV, HK, 16>(v, ug, bg, dg, has, slice, a.pack_region, lane, acc);
                     else
-                        process_packed<S, PV, HK, 32>(a, ug, bg, dg, has, slice, a.pack_region, lane, acc);
+                        process_packed<S, PV, HK, 32>(v, ug, bg, dg, has, slice, a.pack_region, lane, acc);
                     i += np;
                 }
             }
         });
     }
-    add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);
+    if constexpr (MULTI) sink.to(nullptr, acc, lane);
+    else add_workgroup_total(a, acc, s_acc, tid, lane, wave, nw);
 }
 
 typedef void (*KernelFn)(CountArgs);
 
-template <int S, bool HUB, bool SW>
+template <int S, bool HUB, bool SW, bool MULTI>
 KernelFn pick_hk(bool pv, uint32_t hk) {
     if constexpr (HUB) {
-        if (pv) return hk ? tc_hub_kernel<S, true, 1> : tc_hub_kernel<S, true, 0>;
-        return hk ? tc_hub_kernel<S, false, 1> : tc_hub_kernel<S, false, 0>;
+        if (pv) return hk ? tc_hub_kernel<S, true, 1, MULTI> : tc_hub_kernel<S, true, 0, MULTI>;
+        return hk ? tc_hub_kernel<S, false, 1, MULTI> : tc_hub_kernel<S, false, 0, MULTI>;
     } else {
-        if (pv) return hk ? tc_count_kernel<S, true, 1, SW> : tc_count_kernel<S, true, 0, SW>;
-        return hk ? tc_count_kernel<S, false, 1, SW> : tc_count_kernel<S, false, 0, SW>;
+        if (pv) return hk ? tc_count_kernel<S, true, 1, SW, MULTI> : tc_count_kernel<S, true, 0, SW, MULTI>;
+        return hk ? tc_count_kernel<S, false, 1, SW, MULTI> : tc_count_kernel<S, false, 0, SW, MULTI>;
     }
 }
 
-template <bool HUB, bool SW>
+template <bool HUB, bool SW, bool MULTI>
 KernelFn pick(uint32_t S, bool pv, uint32_t hk) {
     switch (S) {
-        case 1: return pick_hk<1, HUB, SW>(pv, hk);
-        case 2: return pick_hk<2, HUB, SW>(pv, hk);
-        case 4: return pick_hk<4, HUB, SW>(pv, hk);
+        case 1: return pick_hk<1, HUB, SW, MULTI>(pv, hk);
+        case 2: return pick_hk<2, HUB, SW, MULTI>(pv, hk);
+        case 4: return pick_hk<4, HUB, SW, MULTI>(pv, hk);
         default: return nullptr;
     }
 }
 
-KernelFn pick_kernel(bool hub, bool sw, uint32_t S, bool pv, uint32_t hk) {
-    if (hub) return pick<true, false>(S, pv, hk);
-    return sw ? pick<false, true>(S, pv, hk) : pick<false, false>(S, pv, hk);
+// Kernel variant: the large-vertex kernel or the main one; subwave probe assignment (main kernel,
+// single graph only); graphs from a multi-graph header.
+KernelFn pick_kernel(bool hub, bool sw, bool multi, uint32_t S, bool pv, uint32_t hk) {
+    if (multi) return hub ? pick<true, false, true>(S, pv, hk) : pick<false, false, true>(S, pv, hk);
+    if (hub) return pick<true, false, false>(S, pv, hk);
+    return sw ? pick<false, true, false>(S, pv, hk) : pick<false, false, false>(S, pv, hk);
 }
 
-}  // namespace
-
-hipError_t count_kernel_info(bool hub, bool sw, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
-                             uint32_t lds_bytes, int* blocks_per_cu) {
-    KernelFn f = pick_kernel(hub, sw, S, pv, hash_kind);
+hipError_t kernel_info(KernelFn f, uint32_t threads, uint32_t lds_bytes, int* blocks_per_cu) {
     if (!f) return hipErrorInvalidValue;
     if (lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(f),
@@ -984,18 +1095,141 @@ hipError_t count_kernel_info(bool hub, bool sw, uint32_t S, bool pv, uint32_t ha
                                                         (int)threads, (size_t)lds_bytes);
 }
 
+}  // namespace
+
+hipError_t count_kernel_info(bool hub, bool sw, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
+                             uint32_t lds_bytes, int* blocks_per_cu) {
+    return kernel_info(pick_kernel(hub, sw, false, S, pv, hash_kind), threads, lds_bytes, blocks_per_cu);
+}
+
+hipError_t count_kernel_info_multi(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
+                                   uint32_t lds_bytes, int* blocks_per_cu) {
+    return kernel_info(pick_kernel(hub, false, true, S, pv, hash_kind), threads, lds_bytes, blocks_per_cu);
+}
+
 hipError_t count_kernel_static_lds(uint32_t* bytes) {
     hipFuncAttributes attr{};
-    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(pick_kernel(true, false, 4, true, 0)));
-    if (e == hipSuccess) *bytes = (uint32_t)attr.sharedSizeBytes;
-    return e;
+    uint32_t most = 0;
+    for (int multi = 0; multi < 2; ++multi) {
+        hipError_t e = hipFuncGetAttributes(&attr,
+                                            reinterpret_cast<const void*>(pick_kernel(true, false, multi, 4, true, 0)));
+        if (e != hipSuccess) return e;
+        if ((uint32_t)attr.sharedSizeBytes > most) most = (uint32_t)attr.sharedSizeBytes;
+    }
+    *bytes = most;
+    return hipSuccess;
 }
 
 hipError_t count_launch(bool hub, bool sw, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
                         uint32_t lds_bytes, const CountArgs& a, hipStream_t stream) {
-    KernelFn f = pick_kernel(hub, sw, S, pv, hash_kind);
+    KernelFn f = pick_kernel(hub, sw, false, S, pv, hash_kind);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(grid), dim3(threads), lds_bytes, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t count_launch_multi(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
+                              uint32_t lds_bytes, const CountArgs& a, hipStream_t stream) {
+    KernelFn f = pick_kernel(hub, false, true, S, pv, hash_kind);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(threads), lds_bytes, stream, a);
+    return hipGetLastError();
+}
+
+namespace {
+
+// Multi-graph set-up: every workgroup clears a grid-stride share of the totals and (per-vertex mode)
+// of the staging; workgroup 0 clears the queue heads and forms, for every bin, the exclusive prefix
+// over the handles of their fetch counts (ceil(bin size / per_fetch)) and the bin totals.
+__global__ void __launch_bounds__(1024) k_multi_prepare(MultiHeader* H) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nw = blockDim.x >> 6;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + tid; i < H->n_totals; i += stride) H->totals[i] = 0;
+    if (H->pv)
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + tid; i < H->n_total; i += stride) H->tv[i] = 0;
+    if (blockIdx.x != 0) return;
+    __shared__ uint32_t s_wave[kBins][kMaxWaves];
+    __shared__ uint32_t s_carry[kBins], s_items[kBins];
+    for (uint32_t i = tid; i < kHeadWords; i += blockDim.x) H->heads[i] = 0;
+    if (tid < kBins) {
+        s_carry[tid] = 0;
+        s_items[tid] = 0;
+    }
+    __syncthreads();
+    const uint32_t k = H->k;
+    for (uint32_t g0 = 0; g0 < k; g0 += blockDim.x) {
+        const uint32_t g = g0 + tid;
+        uint32_t f[kBins];
+        const GraphMeta* m = g < k ? H->desc[g].meta : nullptr;
+#pragma unroll
+        for (uint32_t b = 0; b < kBins; ++b) {
+            const uint32_t nb = m ? m->bins[b] : 0u;
+            if (nb) atomicAdd(&s_items[b], nb);
+            f[b] = (nb + H->per_fetch[b] - 1) / H->per_fetch[b];
+        }
+        uint32_t incl[kBins];
+#pragma unroll
+        for (uint32_t b = 0; b < kBins; ++b) {
+            incl[b] = wave_incl_scan(f[b]);
+            if (lane == 63) s_wave[b][wave] = incl[b];
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t b = 0; b < kBins; ++b) {
+            uint32_t before = s_carry[b];
+            for (uint32_t w = 0; w < wave; ++w) before += s_wave[b][w];
+            if (g < k) H->pre[b * (k + 1) + g] = before + incl[b] - f[b];
+        }
+        __syncthreads();
+        if (tid < kBins) {
+            uint32_t t = 0;
+            for (uint32_t w = 0; w < nw; ++w) t += s_wave[tid][w];
+            s_carry[tid] += t;
+        }
+        __syncthreads();
+    }
+    if (tid < kBins) {
+        H->pre[tid * (k + 1) + k] = s_carry[tid];
+        H->fetch_tot[tid] = s_carry[tid];
+        H->items_tot[tid] = s_items[tid];
+    }
+}
+
+// Per-vertex output of a multi-graph count: staging entry tv0_g + r holds rank r of handle g, so
+// input vertex x of handle g gets tv[tv0_g + rank_g[x]].  Position p of [0, n_total) is vertex
+// p - tv0_g of the last handle g with tv0_g <= p (handles are laid out one after another); each
+// workgroup takes a contiguous range, each thread finds its handle once and walks forward.
+__global__ void __launch_bounds__(256) k_multi_gather(const MultiHeader* H) {
+    const unsigned long long n = H->n_total;
+    const uint32_t k = H->k;
+    const unsigned long long per = (n + gridDim.x - 1) / gridDim.x;
+    const unsigned long long p1 = (per * (blockIdx.x + 1) < n) ? per * (blockIdx.x + 1) : n;
+    unsigned long long p = per * blockIdx.x + threadIdx.x;
+    if (p >= p1) return;
+    const MultiDesc* D = H->desc;
+    uint32_t lo = 0, hi = k - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        if (D[mid].tv0 <= p) lo = mid; else hi = mid - 1;
+    }
+    uint32_t g = lo;
+    for (; p < p1; p += blockDim.x) {
+        while (g + 1 < k && D[g + 1].tv0 <= p) ++g;
+        const MultiDesc& d = D[g];
+        const unsigned long long x = p - d.tv0;
+        d.out[x] = H->tv[d.tv0 + d.rank[x]];
+    }
+}
+
+}  // namespace
+
+hipError_t multi_prepare(MultiHeader* hdr, int cu_count, hipStream_t stream) {
+    hipLaunchKernelGGL(k_multi_prepare, dim3((uint32_t)(cu_count > 0 ? cu_count : 1)), dim3(1024), 0, stream, hdr);
+    return hipGetLastError();
+}
+
+hipError_t multi_gather(const MultiHeader* hdr, int cu_count, hipStream_t stream) {
+    hipLaunchKernelGGL(k_multi_gather, dim3((uint32_t)(cu_count > 0 ? 4 * cu_count : 1)), dim3(256), 0, stream, hdr);
     return hipGetLastError();
 }
 

@@ -193,7 +193,46 @@ struct Layout {
     uint32_t hub_wgs;
 };
 
+// Several built graphs counted by one launch sequence (tc_count_graphs).  The host writes a
+// MultiHeader and one MultiDesc per graph handle into the start of the caller's workspace before
+// the launches; every size the launches need (k, vertex totals, table sizes) is read from there,
+// so one captured launch sequence serves any set of graphs that fits the workspace.
+constexpr uint32_t kBins = 5;  // scheduled bins: global table, large LDS, workgroup, wavefront, packed
+struct MultiDesc {
+    const GraphMeta* meta;           // null when the handle holds no scheduled vertex (empty graph)
+    const uint32_t* off;             // [n + 1] 32-bit CSR offsets
+    const uint32_t* col;
+    const uint32_t* items;
+    const uint32_t* rank;            // [n] input id -> rank (for the per-vertex gather)
+    const uint32_t* gid;             // batch handles: graph of each rank; else null
+    unsigned long long* totals;      // the handle's k totals (one for a single graph)
+    unsigned long long* out;         // per-vertex output, input-id order, or null
+    unsigned long long tv0;          // first entry of the handle's per-vertex staging
+    uint32_t n;
+    uint32_t wide;                   // 64-bit list addressing in the probe
+};
+static_assert(sizeof(MultiDesc) == 80, "descriptor layout is shared with the host");
+struct MultiHeader {
+    uint32_t k;                      // graph handles
+    uint32_t pv;                     // per-vertex output requested
+    unsigned long long n_total;      // sum of the handles' vertex counts (per-vertex staging entries)
+    unsigned long long n_totals;     // sum of the handles' graph counts (entries of the totals array)
+    unsigned long long* totals;      // all totals, handle after handle
+    const MultiDesc* desc;           // [k]
+    uint32_t* pre;                   // [kBins][k + 1]: exclusive prefix over handles of each bin's fetches
+    unsigned long long* tv;          // [n_total] per-vertex staging in rank space
+    uint32_t* heads;                 // [kHeadWords] queue heads
+    uint32_t* hub;                   // global-memory tables: hub_wgs regions of hub_words words
+    unsigned long long hub_words;
+    uint32_t per_fetch[kBins];       // vertices per queue fetch of each bin (host-written)
+    uint32_t items_tot[kBins];       // scheduled vertices of each bin over all handles (device-written)
+    uint32_t fetch_tot[kBins];       // fetches of each bin over all handles (device-written)
+    uint32_t pad[29];
+};
+static_assert(sizeof(MultiHeader) == 256, "header is one 256-byte block");
+
 struct CountArgs {
+    const MultiHeader* multi;        // several graphs (per-graph fields below come from its descriptors)
     const GraphMeta* meta;
     const uint32_t* off;  // [n + 1] 32-bit CSR offsets (half the cache footprint of the 64-bit ones)
     const uint32_t* col;
@@ -258,6 +297,12 @@ hipError_t simple_capacity(uint32_t lds_bytes, uint32_t load_pct, uint32_t* max_
 hipError_t simple_launch(bool edge, bool build_only, uint32_t lds_bytes, int cu_count, const SimpleArgs& a,
                          hipStream_t stream);
 
+// tc_count.hip: the multi-graph steps around the count launches, all sized from the header at
+// `hdr`: clear the totals, queue heads and per-vertex staging and form the per-bin fetch prefixes
+// (before), and map the staging back to each handle's input ids (after, per-vertex mode).
+hipError_t multi_prepare(MultiHeader* hdr, int cu_count, hipStream_t stream);
+hipError_t multi_gather(const MultiHeader* hdr, int cu_count, hipStream_t stream);
+
 // tc_count.hip.  `hub` selects the large-vertex kernel (bins 0 and 1) instead of the main one; `sw` the
 // main kernel with subwave probe assignment.
 hipError_t count_kernel_info(bool hub, bool sw, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
@@ -265,5 +310,10 @@ hipError_t count_kernel_info(bool hub, bool sw, uint32_t S, bool pv, uint32_t ha
 hipError_t count_kernel_static_lds(uint32_t* bytes);
 hipError_t count_launch(bool hub, bool sw, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
                         uint32_t lds_bytes, const CountArgs& a, hipStream_t stream);
+// `multi` selects the kernel variants that take their graphs from a.multi.
+hipError_t count_kernel_info_multi(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t threads,
+                                   uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t count_launch_multi(bool hub, uint32_t S, bool pv, uint32_t hash_kind, uint32_t grid, uint32_t threads,
+                              uint32_t lds_bytes, const CountArgs& a, hipStream_t stream);
 
 }  // namespace tc

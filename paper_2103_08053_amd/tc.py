@@ -24,6 +24,7 @@ EXPORTS = [
     "tc_timing_enable", "tc_timing_last", "tc_batch_footprint", "tc_batch_build", "tc_graph_count_each",
     "tc_graph_count_replay", "tc_graph_k", "tc_graph_count_shard", "tc_graph_collisions",
     "tc_graph_count_simple", "tc_graph_bin_work", "tc_vc_locate", "tc_wide_list_addressing",
+    "tc_count_graphs_bytes", "tc_count_graphs", "tc_count_graphs_replay",
 ]
 
 
@@ -138,6 +139,9 @@ def load_library(path: str = LIB_PATH):
         "tc_timing_last": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
         "tc_vc_locate": [ctypes.POINTER(u32), u32, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)],
         "tc_wide_list_addressing": [u64, u32, ctypes.POINTER(i32)],
+        "tc_count_graphs_bytes": [vp, u32, u64, u64, i32, ctypes.POINTER(u64)],
+        "tc_count_graphs": [vp, u32, ctypes.POINTER(vp), vp, ctypes.POINTER(vp), vp, u64, vp],
+        "tc_count_graphs_replay": [vp, u32, ctypes.POINTER(vp), vp, ctypes.POINTER(vp), vp, u64, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -276,6 +280,49 @@ class Context:
 
     def build(self, src, dst, n: int, stream=None) -> "Graph":
         return Graph(self, src, dst, n, stream=stream)
+
+    def count_graphs_bytes(self, k: int, n_total: int, m_max: int, per_vertex: bool = True) -> int:
+        """Workspace bytes of :meth:`count_graphs` for up to k handles, n_total vertices, m_max samples each."""
+        b = ctypes.c_uint64()
+        _check(self.lib.tc_count_graphs_bytes(self.h, k, n_total, m_max, int(per_vertex), ctypes.byref(b)), self.h)
+        return b.value
+
+    def count_graphs_async(self, graphs, totals, per_vertex_outs=None, workspace=None, stream=None,
+                           replay: bool = False):
+        """Enqueue one count of built handles ``graphs`` (tc_count_graphs / tc_count_graphs_replay):
+        ``totals`` is a device int64 tensor with one entry per graph (batch handles hold several);
+        ``per_vertex_outs`` None or one device int64 tensor per handle.  Returns the workspace used."""
+        torch = _torch()
+        k = len(graphs)
+        hs = (ctypes.c_void_p * k)(*[g.h.value for g in graphs])
+        ws = workspace
+        if ws is None:
+            need = self.count_graphs_bytes(k, sum(g.n for g in graphs), max(g.m_in for g in graphs),
+                                           per_vertex_outs is not None)
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=totals.device)
+        pvs = None
+        if per_vertex_outs is not None:
+            pvs = (ctypes.c_void_p * k)(*[t.data_ptr() if t is not None else 0 for t in per_vertex_outs])
+        fn = self.lib.tc_count_graphs_replay if replay else self.lib.tc_count_graphs
+        _check(fn(self.h, k, hs, _ptr(totals), pvs, _ptr(ws), ws.numel(), _stream_ptr(stream)), self.h)
+        return ws
+
+    def count_graphs(self, graphs, per_vertex: bool = False, workspace=None, stream=None, replay: bool = False):
+        """Count built handles (:class:`Graph` / :class:`Batch`) together.  Returns (totals, per-vertex):
+        totals[g] is an int for a single graph and a list for a batch handle; per-vertex is None or a
+        list of device tensors."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        nt = sum(g.k for g in graphs)
+        totals = torch.empty(max(nt, 1), dtype=torch.int64, device=dev)
+        pvs = [torch.empty(max(g.n, 1), dtype=torch.int64, device=dev) for g in graphs] if per_vertex else None
+        self.count_graphs_async(graphs, totals, pvs, workspace=workspace, stream=stream, replay=replay)
+        flat = totals.cpu().tolist()
+        out, t0 = [], 0
+        for g in graphs:
+            out.append(flat[t0] if g.k == 1 else flat[t0:t0 + g.k])
+            t0 += g.k
+        return out, ([p[: g.n] for p, g in zip(pvs, graphs)] if per_vertex else None)
 
 
 class Graph:

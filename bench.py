@@ -199,8 +199,10 @@ def cpu_baseline(g, info, total: int, stride: int = 1):
 
 
 def run_batch(args):
-    """Batch of small graphs: one union build + one persistent count launch per
-    step (graphs/s), against a loop of per-graph plain tc_count calls."""
+    """Batch of small graphs.  A step: one union build (tc_batch_build) + one count of it through
+    tc_count_graphs_replay (a HIP graph captured on the first call, replayed for every later batch)
+    = graphs/s; against a loop of per-graph plain tc_count calls.  Also reported: the same graphs
+    each built on its own and counted together by one replayed tc_count_graphs call."""
     import ctypes
 
     import numpy as np
@@ -234,18 +236,27 @@ def run_batch(args):
     sb, tb = ctx.batch_footprint(len(graphs), n_tot, m_tot)
     storage = torch.empty(sb, dtype=torch.uint8, device=dev)
     temp = torch.empty(tb, dtype=torch.uint8, device=dev)
+    ws = torch.empty(ctx.count_graphs_bytes(1, n_tot, m_tot, per_vertex=False), dtype=torch.uint8, device=dev)
     scratch = torch.empty(ctx.scratch_bytes(n_tot, m_tot), dtype=torch.uint8, device=dev)
     totals = torch.empty(len(graphs), dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
     ref = torch.tensor(b0.count()[0], dtype=torch.int64, device=dev)
     b0.release()
 
-    def step():
+    def build():
         h = ctypes.c_void_p()
         _check(ctx.lib.tc_batch_build(ctx.h, len(graphs), n_tot, m_tot, _ptr(voff), _ptr(eoff), _ptr(src), _ptr(dst),
                                       _ptr(storage), sb, _ptr(temp), tb, _stream_ptr(stream), ctypes.byref(h)), ctx.h)
-        _check(ctx.lib.tc_graph_count_each(ctx.h, h, _ptr(totals), None, _ptr(scratch), scratch.numel(),
-                                           _stream_ptr(stream)), ctx.h)
+        return h
+
+    def count_replay(h):
+        hs = (ctypes.c_void_p * 1)(h.value)
+        _check(ctx.lib.tc_count_graphs_replay(ctx.h, 1, hs, _ptr(totals), None, _ptr(ws), ws.numel(),
+                                              _stream_ptr(stream)), ctx.h)
+
+    def step():
+        h = build()
+        count_replay(h)
         return h
 
     for _ in range(args.warmup):
@@ -257,9 +268,46 @@ def run_batch(args):
         hs.append(step())
     torch.cuda.synchronize()
     batch_s = (time.perf_counter() - t) / args.steps
+    assert torch.equal(totals, ref)
+    # the count alone: replayed vs eager (tc_graph_count_each), HIP events on the stream
+    h = hs[-1]
+
+    def timed(fn, reps=5):
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return sorted(ms)[len(ms) // 2]
+
+    replay_ms = timed(lambda: count_replay(h))
+    assert torch.equal(totals, ref)
+    eager_ms = timed(lambda: _check(ctx.lib.tc_graph_count_each(ctx.h, h, _ptr(totals), None, _ptr(scratch),
+                                                                 scratch.numel(), _stream_ptr(stream)), ctx.h))
+    assert torch.equal(totals, ref)
+    build_ms = timed(lambda: ctx.lib.tc_graph_release(build()), reps=3)
     for h in hs:
         ctx.lib.tc_graph_release(h)
-    assert torch.equal(totals, ref)
+    del storage, temp, scratch
+    # the same graphs built one by one, counted together by one replayed tc_count_graphs call
+    t = time.perf_counter()
+    each = [ctx.build(torch.from_numpy(g.src.view(np.int32)).to(dev), torch.from_numpy(g.dst.view(np.int32)).to(dev),
+                      g.n) for g in graphs]
+    torch.cuda.synchronize()
+    each_build_s = time.perf_counter() - t
+    ws2 = torch.empty(ctx.count_graphs_bytes(len(each), n_tot, max(g.m_in for g in graphs), per_vertex=False),
+                      dtype=torch.uint8, device=dev)
+    tot2 = torch.empty(len(graphs), dtype=torch.int64, device=dev)
+    ctx.count_graphs_async(each, tot2, None, workspace=ws2, replay=True)
+    torch.cuda.synchronize()
+    each_ms = timed(lambda: ctx.count_graphs_async(each, tot2, None, workspace=ws2, replay=True))
+    assert torch.equal(tot2, ref)
+    for e in each:
+        e.release()
+    del each
     # per-graph plain path on a sample, scaled (each call: build + count + readback)
     sample = graphs[:: max(1, len(graphs) // args.plain_sample)]
     dsrc = [torch.from_numpy(g.src.view(np.int32)).to(dev) for g in sample]
@@ -272,13 +320,15 @@ def run_batch(args):
     idx = list(range(0, len(graphs), max(1, len(graphs) // args.plain_sample)))
     assert all(plain[i] == refl[j] for i, j in enumerate(idx))
     out = {
-        "metric": "batched graphs/s (one build + one persistent count launch) vs per-graph plain launches",
+        "metric": "batched graphs/s (one union build + one replayed count launch sequence) vs per-graph plain launches",
         "value": len(graphs) / batch_s, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": batch_s * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{len(graphs)} graphs: even ER (M = n k), odd BA (k in 4..16), n log-uniform "
                                f"[100, 50000], SplitMix64 seeds", "n_total": n_tot, "m_total": m_tot,
                    "params": vars(params), "tuned": tuned},
+        "build_ms": build_ms, "count_replay_ms": replay_ms, "count_eager_ms": eager_ms,
+        "separately_built": {"graphs_built_one_by_one_s": each_build_s, "one_count_graphs_replay_ms": each_ms},
         "plain_graphs_per_s": len(graphs) / plain_s,
         "speedup_vs_plain": plain_s / batch_s,
         "batched_teps_input_edges": m_tot / batch_s,
@@ -307,47 +357,85 @@ def run_shards(args, ctx, graph, info, total, per_vertex):
             "triangles_max_over_mean": max(tots) / (sum(tots) / len(tots))}
 
 
-def run_serve(args):
-    """Poisson request stream over a pinned-host pool; continuous batching vs FIFO plain path."""
-    import numpy as np
+def serve_once(args, pool, want, rate: float, warm: float, dur: float, mode: str, seed: int = 11):
+    """One open-loop Poisson run over the pool: `warm` seconds of warm-up, `dur` measured; the loop
+    stops 2 s after the window.  Every answered request is checked against the oracle's count of
+    its graph.  Returns the window's stats."""
     import torch
 
-    import graphgen.workloads as W
     from paper_2103_08053_amd import Context, serve
+    arrivals = W_poisson(rate, warm + dur, seed)
+    reqs = [serve.Request(i, *pool[i % len(pool)]) for i in range(len(arrivals))]
+    torch.cuda.synchronize()
+    stop = warm + dur + 2.0
+    if mode == "fifo":
+        serve_stats = serve.serve_fifo(Context(0), reqs, arrivals, stop_after=stop)
+        counts, extra = serve_stats["batches"], {}
+    else:
+        srv = serve.Server(0, hbm_budget=args.hbm_budget_gb << 30, max_batch=args.max_batch,
+                           max_inflight=args.max_inflight, build=mode)
+        serve_stats = srv.run(reqs, arrivals, stop_after=stop)
+        counts = serve_stats["batches"]
+        extra = {"direct": serve_stats["direct"], "device_busy_frac": serve_stats["device_busy_frac"]}
+    bad = [r.rid for r in reqs if r.done >= 0 and r.total != want[r.rid % len(pool)]]
+    assert not bad, f"{mode}: {len(bad)} answers differ from the oracle"
+    st = serve.summarize(reqs, serve_stats["wall_s"], counts, window=(warm, warm + dur))
+    st.update(extra)
+    st["rate"] = rate
+    st["oracle_checked"] = sum(1 for r in reqs if r.done >= 0)
+    log(f"[bench] serve {mode} at {rate}/s: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, "
+        f"{st['throughput_rps']:.0f} req/s, unanswered {st['unanswered']}")
+    return st
+
+
+def W_poisson(rate, duration, seed):
+    import graphgen.workloads as W
+    return W.poisson_arrivals(rate, duration, seed=seed)
+
+
+def run_serve(args):
+    """Open-loop Poisson stream over a pinned-host pool: continuous batching (each request built on
+    arrival, counted with the others by one replayed launch sequence) vs the plain FIFO path, at
+    the configured rate with a warm-up and a measured window, plus a rate sweep for the highest
+    rate whose p99 stays within the bound.  Every answer is checked against the oracle."""
+    import graphgen.workloads as W
+    import oracle
+    from paper_2103_08053_amd import serve
 
     t0 = time.time()
     specs = W.serving_pool(args.pool, seed=7, rmat_scales=(10, args.serve_max_scale))
-    pool = [W.serving_graph(sp) for sp in specs]
-    log(f"[bench] serving pool of {len(pool)} graphs in {time.time() - t0:.1f}s "
-        f"({sum(g.m_in for g in pool) / 1e6:.1f} M samples)")
-    arrivals = W.poisson_arrivals(args.rate, args.duration, seed=11)
-    ctx0 = Context(0)
-    alone = [ctx0.count(g.src, g.dst, g.n)[0] for g in pool]  # each graph counted on its own
+    graphs = [W.serving_graph(sp) for sp in specs]
+    log(f"[bench] serving pool of {len(graphs)} graphs in {time.time() - t0:.1f}s "
+        f"({sum(g.m_in for g in graphs) / 1e6:.1f} M samples)")
+    want = []
+    t0 = time.time()
+    for i, g in enumerate(graphs):
+        want.append(oracle.count(g.n, g.src, g.dst).total)
+        if i % 8 == 7:
+            log(f"[bench] oracle: {i + 1}/{len(graphs)} pool graphs counted ({time.time() - t0:.0f}s)")
+    pool = [(g.n, serve._pinned(g.src), serve._pinned(g.dst)) for g in graphs]  # one pinned copy per graph
+    del graphs
     res = {}
-    pinned = [(g.n, serve._pinned(g.src), serve._pinned(g.dst)) for g in pool]  # one pinned copy per graph
-    for mode in ("batched", "plain"):
-        reqs = [serve.Request(i, *pinned[i % len(pool)]) for i in range(len(arrivals))]
-        torch.cuda.synchronize()
-        if mode == "batched":
-            srv = serve.Server(0, hbm_budget=args.hbm_budget_gb << 30, max_batch=args.max_batch,
-                               max_inflight=args.max_inflight)
-            stats = srv.run(reqs, arrivals)
-        else:
-            stats = serve.serve_fifo(Context(0), reqs, arrivals)
-        res[mode] = stats
-        bad = [r.rid for r in reqs if r.total != alone[r.rid % len(pool)]]
-        assert not bad, f"{mode}: {len(bad)} requests differ from the graph counted alone"
-        log(f"[bench] serve {mode}: {stats}")
+    for mode in args.serve_modes.split(","):
+        res[mode] = serve_once(args, pool, want, args.rate, args.serve_warmup, args.duration, mode)
+    sweep = []
+    if args.sweep:
+        for rate in [float(x) for x in args.sweep.split(",")]:
+            sweep.append(serve_once(args, pool, want, rate, 2.0, args.sweep_window, "each", seed=13))
+    ok = [s["rate"] for s in sweep if s["p99_ms"] <= args.p99_bound_ms and s["unanswered"] == 0]
+    main = res.get("each") or next(iter(res.values()))
     out = {
         "metric": "served requests: p50/p99 latency and throughput, continuous batching vs plain FIFO",
-        "value": res["batched"]["throughput_rps"], "unit": "requests/s", "n_gpus": 1, "steps": len(arrivals),
-        "warmup": 0, "ms_per_step": 1e3 / max(res["batched"]["throughput_rps"], 1e-9), "higher_is_better": True,
+        "value": main["throughput_rps"], "unit": "requests/s", "n_gpus": 1, "steps": main["requests"],
+        "warmup": 0, "ms_per_step": 1e3 / max(main["throughput_rps"], 1e-9), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"Poisson {args.rate}/s for {args.duration}s over {len(pool)} graphs (R-MAT scale "
-                               f"10-{args.serve_max_scale} ef 16, BA n 1e3-1e6 k 4-16)",
+        "config": {"workload": f"Poisson {args.rate}/s, {args.serve_warmup} s warm-up + {args.duration} s measured, "
+                               f"over {len(pool)} graphs (R-MAT scale 10-{args.serve_max_scale} ef 16, BA n 1e3-1e6 "
+                               f"k 4-16) in pinned host memory",
                    "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
                    "max_inflight": args.max_inflight},
-        "batched": res["batched"], "plain": res["plain"],
+        "modes": res, "sweep": sweep, "p99_bound_ms": args.p99_bound_ms,
+        "sustainable_rate": max(ok) if ok else None,
     }
     print(json.dumps(out), flush=True)
 
@@ -367,9 +455,15 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=256)
     ap.add_argument("--tune", action="store_true")
-    ap.add_argument("--pool", type=int, default=48)
+    ap.add_argument("--pool", type=int, default=96)
     ap.add_argument("--rate", type=float, default=2000.0)
-    ap.add_argument("--duration", type=float, default=2.0)
+    ap.add_argument("--duration", type=float, default=30.0, help="serving: measured window (s)")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="serving: warm-up before the window (s)")
+    ap.add_argument("--serve-modes", default="each,union,fifo",
+                    help="serving: each (build on arrival + tc_count_graphs), union (batch build), fifo (plain)")
+    ap.add_argument("--sweep", default="", help="serving: comma-separated rates for the sustainable-rate search")
+    ap.add_argument("--sweep-window", type=float, default=8.0)
+    ap.add_argument("--p99-bound-ms", type=float, default=100.0)
     ap.add_argument("--serve-max-scale", type=int, default=20)
     ap.add_argument("--hbm-budget-gb", type=int, default=96)
     ap.add_argument("--max-batch", type=int, default=256)

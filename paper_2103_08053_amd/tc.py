@@ -330,7 +330,7 @@ class Graph:
     device; count it many times.  Use :meth:`Context.build` or :class:`Batch`."""
 
     def __init__(self, ctx: Context, src, dst, n: int, stream=None, storage=None, temp=None, _batch=None,
-                 sync: bool = True):
+                 sync: bool = True, scratch: bool = True):
         torch = _torch()
         self.ctx = ctx
         self.n = n
@@ -344,7 +344,10 @@ class Graph:
             sb, tb = ctx.batch_footprint(_batch[0], n, self.m_in)
         self.storage = storage if storage is not None else torch.empty(max(sb, 1), dtype=torch.uint8, device=dev)
         tmp = temp if temp is not None else torch.empty(max(tb, 1), dtype=torch.uint8, device=dev)
-        self.scratch = torch.empty(max(ctx.scratch_bytes(n, self.m_in), 1), dtype=torch.uint8, device=dev)
+        # count scratch of this graph's own count calls (not needed when it is only counted through
+        # Context.count_graphs, which brings its own workspace)
+        self.scratch = (torch.empty(max(ctx.scratch_bytes(n, self.m_in), 1), dtype=torch.uint8, device=dev)
+                        if scratch else None)
         h = ctypes.c_void_p()
         if _batch is None:
             _check(ctx.lib.tc_graph_build(ctx.h, n, self.m_in, _ptr(s), _ptr(d), _ptr(self.storage),

@@ -15,9 +15,11 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def test_served_results_equal_alone():
-    """Requests served in mixed, overlapping batches get exactly the count of
-    their graph counted alone."""
+@pytest.mark.parametrize("build", ["each", "union"])
+def test_served_results_equal_alone(build):
+    """Requests served in mixed, overlapping counts (each request built on arrival and counted with
+    the others by one replayed launch sequence, or built together as a union) get exactly the
+    count of their graph counted alone, which is the oracle's."""
     from paper_2103_08053_amd import Context, serve
     pool = [gg.rmat(s, 16, seed=s) for s in (10, 12, 14)] + [gg.barabasi_albert(20000, k, seed=k) for k in (4, 9)] \
         + [gg.complete(60), gg.torus3d(8)]
@@ -29,7 +31,7 @@ def test_served_results_equal_alone():
     pinned = [serve.make_request(i, g.n, g.src, g.dst) for i, g in enumerate(pool)]
     reqs = [serve.Request(i, pinned[i % len(pool)].n, pinned[i % len(pool)].src, pinned[i % len(pool)].dst)
             for i in range(len(arrivals))]
-    srv = serve.Server(0, hbm_budget=2 << 30, max_batch=32)
+    srv = serve.Server(0, hbm_budget=2 << 30, max_batch=32, build=build)
     stats = srv.run(reqs, arrivals)
     say(f"[gpu] {stats}")
     assert all(r.total == alone[r.rid % len(pool)] for r in reqs)
@@ -90,3 +92,21 @@ def test_idle_requests_go_direct_and_match():
     say(f"[gpu] {stats}")
     assert all(r.total == alone[r.rid % 3] for r in reqs)
     assert stats["direct"] >= 1 and stats["batches"] > stats["direct"]
+
+
+def test_serving_window_and_cutoff():
+    """A burst larger than the device can answer before the cut-off: answered requests are the
+    oracle's counts, unanswered ones are reported, and the measured window excludes the warm-up."""
+    from paper_2103_08053_amd import serve
+    pool = [gg.rmat(13, 16, seed=5), gg.barabasi_albert(30000, 8, seed=2)]
+    alone = [oracle.count(g.n, g.src, g.dst).total for g in pool]
+    arrivals = np.concatenate([np.linspace(0.0, 0.05, 40), np.linspace(0.2, 0.21, 300)])
+    pinned = [serve.make_request(i, g.n, g.src, g.dst) for i, g in enumerate(pool)]
+    reqs = [serve.Request(i, pinned[i % 2].n, pinned[i % 2].src, pinned[i % 2].dst) for i in range(len(arrivals))]
+    srv = serve.Server(0, hbm_budget=4 << 30, max_batch=16)
+    srv.run(reqs, arrivals, stop_after=0.25)
+    win = serve.summarize(reqs, 0.25, 0, window=(0.1, 0.3))
+    say(f"[gpu] window stats {win}")
+    assert win["requests"] == 300 and win["answered"] + win["unanswered"] == 300
+    assert all(r.total == alone[r.rid % 2] for r in reqs if r.done >= 0)
+    assert sum(1 for r in reqs if r.done >= 0) >= 40

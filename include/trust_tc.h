@@ -15,7 +15,9 @@
  * Conventions shared by every call:
  *   - Memory: every device buffer is owned by the caller.  The library never
  *     allocates or frees device memory; its scratch space comes from a
- *     caller-provided workspace sized by the matching *_bytes query.  Host
+ *     caller-provided workspace sized by the matching *_bytes query (except
+ *     tc_graph_count_static, whose scratch is a static buffer that every
+ *     device holds for the life of the process).  Host
  *     memory is allocated only for the opaque handles and a context's pinned
  *     staging buffers (tc_count_graphs).
  *   - Ids: vertex ids are uint32 in [0, n), n <= 2^32 - 1.  Edge samples may
@@ -167,6 +169,19 @@ tc_status tc_count_scratch_bytes(const tc_context* ctx, uint32_t n, uint64_t m_i
 tc_status tc_graph_count(tc_context* ctx, const tc_graph* g, uint64_t* d_total,
                          uint64_t* d_per_vertex, void* d_scratch, uint64_t scratch_bytes,
                          void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): tc_graph_count with its count scratch in a library-owned
+ * static device buffer of TC_STATIC_SCRATCH_BYTES instead of a caller workspace.  Each device the
+ * library runs on holds its own copy of that buffer until the process ends; the call itself
+ * allocates nothing.  TC_E_NOMEM when the graph's scratch (tc_count_scratch_bytes with the graph's
+ * n and m_in) exceeds the buffer, TC_E_INVALID for a batch handle.  The buffer keeps the last
+ * call's contents (every call clears what it needs zeroed), and all calls on one device share it:
+ * calls that overlap on one device (other streams, other host threads) race, so order them on one
+ * stream.  Asynchronous on `stream`, as tc_graph_count. */
+#define TC_STATIC_SCRATCH_BYTES (128ull << 20)
+tc_status tc_graph_count_static(tc_context* ctx, const tc_graph* g, uint64_t* d_total, uint64_t* d_per_vertex,
+                                void* stream);
 
 /* Synchronise `stream` and read the graph's summary; returns TC_E_RANGE if
  * the build saw an id >= n. */

@@ -7,11 +7,17 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "tc_internal.h"
+
+// Count scratch of tc_graph_count_static: a library-owned buffer in every device's memory, so that
+// entry point allocates nothing.  In host code `scratch` names a host-side stand-in, not a device
+// address; the device address comes from hipGetSymbolAddress, taken once per device (static_scratch).
+static __device__ __align__(256) unsigned char scratch[TC_STATIC_SCRATCH_BYTES];
 
 struct tc_context {
     int device = 0;
@@ -47,8 +53,33 @@ struct tc_context {
         hipGraphExec_t exec;
     };
     std::vector<MultiCapture> mcap;
+    void* static_scratch = nullptr;  // this device's copy of the library-owned count scratch
     std::vector<Occ> occ;  // resident workgroups per CU, by kernel variant and launch shape
 };
+
+namespace {
+
+// Device address of `scratch` on each device, resolved with that device current the first time a
+// context is created on it (nullptr until then).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_scratch(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+}  // namespace
 
 struct tc_graph {
     tc_context* ctx = nullptr;
@@ -520,6 +551,10 @@ tc_status tc_create(int hip_device, const tc_params* p, tc_context** out) {
             return TC_E_DEVICE;
         }
         c->big_lds_bytes = (uint32_t)((c->lds_per_block_max - static_lds) & ~(size_t)15);
+        if (static_scratch(hip_device, &c->static_scratch) != hipSuccess) {
+            delete c;
+            return TC_E_DEVICE;
+        }
     }
     c->p = q;
     *out = c;
@@ -684,6 +719,20 @@ tc_status tc_graph_count(tc_context* ctx, const tc_graph* g, uint64_t* d_total, 
     if (!d_scratch || scratch_bytes < L.scratch) return fail(ctx, TC_E_NOMEM, "scratch too small");
     if (tc_status s = use_device(ctx)) return s;
     return count_into(ctx, g, d_total, d_per_vertex, d_scratch, L, static_cast<hipStream_t>(stream));
+}
+
+tc_status tc_graph_count_static(tc_context* ctx, const tc_graph* g, uint64_t* d_total, uint64_t* d_per_vertex,
+                                void* stream) {
+    if (!ctx || !g || !d_total) return TC_E_INVALID;
+    if (g->k != 1) return fail(ctx, TC_E_INVALID, "a batch of %u graphs: single graphs only", g->k);
+    ctx->err.clear();
+    if (!ctx->static_scratch) return fail(ctx, TC_E_DEVICE, "static scratch not resolved on device %d", ctx->device);
+    const Layout L = layout(ctx, g->p, g->n, g->m_in);
+    if (L.scratch > TC_STATIC_SCRATCH_BYTES)
+        return fail(ctx, TC_E_NOMEM, "count scratch %llu bytes exceeds the static buffer of %llu bytes",
+                    (unsigned long long)L.scratch, (unsigned long long)TC_STATIC_SCRATCH_BYTES);
+    if (tc_status s = use_device(ctx)) return s;
+    return count_into(ctx, g, d_total, d_per_vertex, ctx->static_scratch, L, static_cast<hipStream_t>(stream));
 }
 
 tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out) {

@@ -24,8 +24,9 @@ EXPORTS = [
     "tc_timing_enable", "tc_timing_last", "tc_batch_footprint", "tc_batch_build", "tc_graph_count_each",
     "tc_graph_count_replay", "tc_graph_k", "tc_graph_count_shard", "tc_graph_collisions",
     "tc_graph_count_simple", "tc_graph_bin_work", "tc_vc_locate", "tc_wide_list_addressing",
-    "tc_count_graphs_bytes", "tc_count_graphs", "tc_count_graphs_replay",
+    "tc_count_graphs_bytes", "tc_count_graphs", "tc_count_graphs_replay", "tc_graph_count_static",
 ]
+TC_STATIC_SCRATCH_BYTES = 128 << 20
 
 
 class TCError(RuntimeError):
@@ -142,6 +143,7 @@ def load_library(path: str = LIB_PATH):
         "tc_count_graphs_bytes": [vp, u32, u64, u64, i32, ctypes.POINTER(u64)],
         "tc_count_graphs": [vp, u32, ctypes.POINTER(vp), vp, ctypes.POINTER(vp), vp, u64, vp],
         "tc_count_graphs_replay": [vp, u32, ctypes.POINTER(vp), vp, ctypes.POINTER(vp), vp, u64, vp],
+        "tc_graph_count_static": [vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

@@ -27,6 +27,13 @@ def test_library_exports_every_declared_symbol():
     assert sorted(tc.EXPORTS) == names
 
 
+def test_static_scratch_size_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define TC_STATIC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", text)
+    assert m, "TC_STATIC_SCRATCH_BYTES not found"
+    assert tc.TC_STATIC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
+
+
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(tc._Params) == 10 * 4
     assert ctypes.sizeof(tc._GraphInfo) == 3 * 8 + 10 * 4

@@ -72,7 +72,8 @@ def feature_key(info, per_vertex: bool, k: int = 1) -> str:
 
 
 def _valid(p: Params) -> bool:
-    return 64 * p.wg_waves <= 1024 and p.wg_lds_bytes * 1 <= 131072
+    # the library's rule: every wavefront keeps a 256-word probe queue and at least 64 table words
+    return 64 * p.wg_waves <= 1024 and p.wg_lds_bytes <= 131072 and p.wg_lds_bytes // 4 >= p.wg_waves * 320
 
 
 class _Workload:

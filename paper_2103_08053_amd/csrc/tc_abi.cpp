@@ -141,6 +141,8 @@ tc_status check_params(const tc_params* p) {
     if (!p || p->struct_size != sizeof(tc_params)) return TC_E_INVALID;
     if (p->wg_waves < 1 || p->wg_waves > tc::kMaxWaves) return TC_E_INVALID;
     if (p->wg_lds_bytes < 4096 || p->wg_lds_bytes > 131072 || p->wg_lds_bytes % 16) return TC_E_INVALID;
+    // every wavefront keeps a probe queue in the LDS and a slice of at least 64 words
+    if (p->wg_lds_bytes / 4 < p->wg_waves * (tc::kQueueWords + 64)) return TC_E_INVALID;
     if (p->slots_per_bucket != 1 && p->slots_per_bucket != 2 && p->slots_per_bucket != 4) return TC_E_INVALID;
     if (p->load_factor_pct < 10 || p->load_factor_pct > 100) return TC_E_INVALID;
     if (p->hash_kind > 1) return TC_E_INVALID;
@@ -153,20 +155,29 @@ tc_status check_params(const tc_params* p) {
     return TC_OK;
 }
 
+// LDS words of the main launch's table region: its LDS minus the wavefronts' probe queues.
+uint32_t wg_table_words(const tc_params& p) { return p.wg_lds_bytes / 4 - p.wg_waves * tc::kQueueWords; }
+
+// A wavefront's slice of the table region.
 uint32_t slice_words(const tc_params& p) {
-    return (p.wg_lds_bytes / 4 / p.wg_waves) & ~3u;
+    return (wg_table_words(p) / p.wg_waves) & ~3u;
 }
+
+// Table region of the large-vertex launch (16 wavefronts, all the LDS a workgroup may have).
+uint32_t big_table_words(const tc_context* ctx) { return ctx->big_lds_bytes / 4 - tc::kMaxWaves * tc::kQueueWords; }
 
 // LDS words of a packed light vertex's table: a quarter of a wavefront slice.
 uint32_t pack_region(const tc_params& p) { return (slice_words(p) / 4) & ~3u; }
 
 tc::BinCaps bin_caps(const tc_context* ctx, const tc_params& p) {
     tc::BinCaps c{};
-    // Capacities assume the per-vertex layout (the larger one), so one binning serves both modes.
-    c.wg_cap = tc::capacity(p.wg_lds_bytes / 4, p.slots_per_bucket, p.load_factor_pct, true);
-    c.wave_cap = tc::capacity(slice_words(p), p.slots_per_bucket, p.load_factor_pct, true);
+    // Capacities assume the per-vertex layout (the larger one), so one binning serves both modes,
+    // and the filter of the LDS tables walked by virtual combination (not in the subwave modes).
+    const bool filt = subwave_lanes(p.flags) == 0;
+    c.wg_cap = tc::capacity(wg_table_words(p), p.slots_per_bucket, p.load_factor_pct, true, filt);
+    c.wave_cap = tc::capacity(slice_words(p), p.slots_per_bucket, p.load_factor_pct, true, filt);
     if (p.wave_max_dplus && p.wave_max_dplus < c.wave_cap) c.wave_cap = p.wave_max_dplus;
-    c.big_cap = tc::capacity(ctx->big_lds_bytes / 4, p.slots_per_bucket, p.load_factor_pct, true);
+    c.big_cap = tc::capacity(big_table_words(ctx), p.slots_per_bucket, p.load_factor_pct, true, true);
     if (c.big_cap < c.wg_cap) c.big_cap = c.wg_cap;
     c.force_wg = (p.flags & TC_F_FORCE_WG) != 0;
     c.force_hub = (p.flags & TC_F_FORCE_HUB) != 0;
@@ -392,11 +403,11 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     const bool rec = record && ctx->timing;
     if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
     if (hub) {
-        a.table_words = launch_lds(ctx, p, true) / 4;
+        a.table_words = big_table_words(ctx);
         HIP_TRY(ctx, tc::count_launch(true, false, p.slots_per_bucket, pv, p.hash_kind, grid_hub, launch_threads(p, true),
                                       launch_lds(ctx, p, true), a, s));
     }
-    a.table_words = p.wg_lds_bytes / 4;
+    a.table_words = wg_table_words(p);
     HIP_TRY(ctx, tc::count_launch(false, a.subwave != 0, p.slots_per_bucket, pv, p.hash_kind, grid,
                                   launch_threads(p, false),
                                   p.wg_lds_bytes, a, s));
@@ -468,10 +479,10 @@ tc_status multi_launches(tc_context* ctx, const tc_params& p, bool pv, tc::Multi
     HIP_TRY(ctx, tc::multi_prepare(hdr, ctx->cu_count, s));
     const bool rec = record && ctx->timing;
     if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
-    a.table_words = launch_lds(ctx, p, true) / 4;
+    a.table_words = big_table_words(ctx);
     HIP_TRY(ctx, tc::count_launch_multi(true, p.slots_per_bucket, pv, p.hash_kind, grid_hub, launch_threads(p, true),
                                         launch_lds(ctx, p, true), a, s));
-    a.table_words = p.wg_lds_bytes / 4;
+    a.table_words = wg_table_words(p);
     HIP_TRY(ctx, tc::count_launch_multi(false, p.slots_per_bucket, pv, p.hash_kind, grid, launch_threads(p, false),
                                         p.wg_lds_bytes, a, s));
     if (rec) {
@@ -863,10 +874,16 @@ tc_status tc_graph_collisions(tc_context* ctx, const tc_graph* g, int per_vertex
     a.col = g->dev.col;
     a.items = g->dev.items;
     a.avail[0] = (uint32_t)L.hub_words;
-    a.avail[1] = ctx->big_lds_bytes / 4;
-    a.avail[2] = p.wg_lds_bytes / 4;
+    a.avail[1] = big_table_words(ctx);
+    a.avail[2] = wg_table_words(p);
     a.avail[3] = slice_words(p);
     a.avail[4] = pack_region(p);
+    const uint32_t filt = subwave_lanes(p.flags) == 0 ? 1u : 0u;
+    a.filt[0] = 0;
+    a.filt[1] = 1;
+    a.filt[2] = filt;
+    a.filt[3] = filt;
+    a.filt[4] = 0;
     a.S = p.slots_per_bucket;
     a.lrecip = tc::load_recip(p.load_factor_pct);
     a.hash_kind = p.hash_kind;

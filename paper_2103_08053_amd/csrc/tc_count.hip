@@ -162,7 +162,8 @@ __device__ __forceinline__ bool lookup_chain(const uint32_t* slots, uint32_t w, 
     return false;
 }
 
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 4;  // chunks per load group (the filter code spells out four)
+static_assert(kUnroll == 4, "filter_group initialises four lane masks");
 
 struct Probe {
     const uint32_t* __restrict__ col;
@@ -171,7 +172,16 @@ struct Probe {
     uint32_t* tslot;  // per-slot hit tallies (per-vertex mode): the slot's element is the triangle's w
     uint32_t* tally;  // per-out-neighbour hit tallies (per-vertex mode): v_k of the triangle
     uint32_t B;
+    const uint32_t* filt;  // filter bit vector of fbits bits (LDS tables)
+    uint32_t fbits;
+    uint32_t flog;         // log2 of the filter's words
+    uint32_t* queue;       // this wavefront's queue: entries {id, k}, kQueueEntries then 64 dummies
 };
+
+// This lane's position among the set lanes of a wave mask (number of set lanes below it).
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
 
 template <int S, bool PV>
 __device__ __forceinline__ void tally_hit(const Probe& pr, uint32_t s, uint32_t k) {
@@ -189,7 +199,7 @@ __device__ __forceinline__ void tally_slot4(const Probe& pr, uint32_t b, uint32_
 
 // Probe the flattened 2-hop range [lo, hi) of the current vertex with one
 // wavefront, walking it in chunks of 64 consecutive indices (consecutive
-// lanes read consecutive words of a list).
+// lanes read consecutive words of a list).  Returns the hits (uniform).
 //
 // Each lane keeps a forward-only cursor as a position in col: `pos` (the
 // word it reads next) and `lim` (end of the current list).  A chunk step is
@@ -198,6 +208,16 @@ __device__ __forceinline__ void tally_slot4(const Probe& pr, uint32_t b, uint32_
 // position is kept as a 32-bit byte offset and loads take the scalar-base
 // form (no 64-bit address arithmetic per chunk).
 //
+// Filter and queue: most probes miss (a few percent hit on skewed graphs), so
+// every probed id first tests its bit of the table's filter (one 4-byte LDS
+// read); only ids whose bit is set (the hits and a few percent of the misses)
+// are appended to the wavefront's queue in LDS.  When the queue cannot take a
+// chunk's survivors, its entries are looked up together, one per lane, in the
+// bucket table (Algorithm 1's intersection step), so the full lookup runs on a
+// nearly full wavefront instead of on every chunk.  The queue keeps the order
+// of the flattened index, so its entries' out-neighbour indices k are
+// non-decreasing: per-vertex tallies of v_k are added once per run of equal k.
+//
 // A lookup whose bucket is full without a match must continue at the next
 // bucket.  Instead of walking that chain while the other 63 lanes wait, the
 // lane parks it (w, bucket[, k]) in registers; parked lookups take one
@@ -205,14 +225,15 @@ __device__ __forceinline__ void tally_slot4(const Probe& pr, uint32_t b, uint32_
 // needs to park another, and at the end of the range.
 //
 // Loads for the next group of kUnroll chunks are issued before the current
-// group is probed (two register sets used in turn); leftover chunks are
-// probed one at a time and the ragged last chunk with a lane predicate.
+// group is filtered (two register sets used in turn); leftover chunks are
+// taken in groups of up to kUnroll and the ragged last chunk with a lane
+// predicate.
 template <int S, bool PV, int HK, bool WIDE>
 __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, uint32_t d, uint32_t lo, uint32_t hi,
                                                               int lane) {
     if (lo >= hi) return 0;
     const uint32_t bmask = pr.B - 1;
-    uint32_t hits = 0;  // per lane; summed across the wavefront at the end (W < 2^32)
+    uint32_t hits = 0;  // uniform (W < 2^32)
     // Cursor: record k holds the lane's next flattened index ii; pos = base_k + ii.
     uint32_t k, pos, lim, base;
     {
@@ -248,9 +269,6 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
     // Parked lookups: word, bucket (and k in per-vertex mode), mask of lanes holding one.
     uint32_t pw = 0, pb = 0, pk = 0;
     unsigned long long pm = 0;
-    // Per-vertex mode: hits of the lane's current out-neighbour k, added to tally[k] when k changes
-    // (hits of one chunk mostly share k; per-hit atomics on one address would serialise).
-    uint32_t acck = k, accn = 0;
 
     auto step_parked = [&]() {
         const unsigned long long mine = pm;
@@ -258,32 +276,48 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         const Bucket<S> v = read_bucket<S>(pr.slots, b);
         const unsigned long long hm = ballot_has<S>(v, pw) & mine;
         const unsigned long long cmask = __ballot(v.v[S - 1] != kEmpty) & mine & ~hm;
-        if constexpr (!PV) hits += (uint32_t)lane_in(hm);
+        hits += (uint32_t)__popcll(hm);
         if constexpr (PV) {
             if (lane_in(hm)) {
                 tally_slot4<S>(pr, b, bucket_pos4<S>(v, pw));
                 atomicAdd(&pr.tally[pk], 1u);
-                ++hits;
             }
         }
         pb = lane_in(cmask) ? b : pb;
         pm = cmask;
     };
 
-    auto resolve = [&](const Bucket<S>& v, uint32_t w, uint32_t b, uint32_t kk, unsigned long long actm) {
-        const unsigned long long hm = ballot_has<S>(v, w) & actm;
-        const unsigned long long cm = __ballot(v.v[S - 1] != kEmpty) & actm & ~hm;
-        if constexpr (!PV) hits += (uint32_t)lane_in(hm);
+    // Look up the qn queued ids (lane i takes entry i) in the bucket table.
+    uint32_t qn = 0;  // uniform: queued entries
+    u32x2* const queue = reinterpret_cast<u32x2*>(pr.queue);
+    auto flush = [&]() {
+        wave_sync();  // the queue writes of every lane are visible
+        const bool act = (uint32_t)lane < qn;
+        const unsigned long long am = qn >= 64u ? ~0ull : ((1ull << qn) - 1ull);
+        uint32_t w = 0, kk = 0;
+        {
+            const u32x2 e = queue[lane];  // entries past qn are stale or dummies: masked off by am
+            w = e.x;
+            if constexpr (PV) kk = e.y;
+        }
+        const uint32_t b = hash_of<HK>(w, pr.B);
+        const Bucket<S> v = read_bucket<S>(pr.slots, b);
+        const unsigned long long hm = ballot_has<S>(v, w) & am;
+        const unsigned long long cm = __ballot(v.v[S - 1] != kEmpty) & am & ~hm;
+        hits += (uint32_t)__popcll(hm);
         if constexpr (PV) {
             const bool hit = lane_in(hm);
-            if (kk != acck) {
-                if (accn) atomicAdd(&pr.tally[acck], accn);
-                hits += accn;
-                acck = kk;
-                accn = 0;
-            }
-            accn += (uint32_t)hit;
             if (hit) tally_slot4<S>(pr, b, bucket_pos4<S>(v, w));
+            // tally[k] += hits of each run of equal k: the run's last lane adds the hits up to and
+            // including it, the run's first lane subtracts the hits below it (modulo 2^32).
+            const uint32_t kprev = (uint32_t)__shfl_up((int)kk, 1, 64);
+            const uint32_t knext = (uint32_t)__shfl_down((int)kk, 1, 64);
+            const uint32_t below = lanes_below(hm);
+            const bool first = act && (lane == 0 || kprev != kk);
+            const bool last = act && ((uint32_t)lane + 1u == qn || knext != kk);
+            const uint32_t upto = below + (hit ? 1u : 0u);
+            if (last && upto) atomicAdd(&pr.tally[kk], upto);
+            if (first && below) atomicSub(&pr.tally[kk], below);
         }
         if (cm) {
             while (cm & pm) step_parked();
@@ -294,28 +328,65 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
             pm |= cm;
             if (__builtin_amdgcn_readfirstlane((uint32_t)__popcll(pm)) >= 32u) step_parked();
         }
+        wave_sync();  // every lane has read its entry before the queue is refilled
+        qn = 0;
+    };
+
+    // A group of up to kUnroll chunks (lanes in am[j]) through the filter: the filter words of all
+    // chunks are read first, then the survivors go to the queue in chunk order (looked up first
+    // when they would overflow it).  Every lane writes: a survivor to its queue position, any other
+    // lane to its own dummy entry.
+    auto append = [&](const unsigned long long sm, uint32_t w, uint32_t kk) {
+        const uint32_t at = lane_in(sm) ? qn + lanes_below(sm) : kQueueEntries + (uint32_t)lane;
+        if constexpr (PV) queue[at] = u32x2{w, kk};
+        else queue[at].x = w;
+        qn += (uint32_t)__popcll(sm);
+    };
+    auto filter_group = [&](const uint32_t (&w)[kUnroll], const uint32_t (&kk)[kUnroll],
+                            const unsigned long long (&am)[kUnroll], uint32_t gcount) {
+        uint32_t fw[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            uint32_t word;
+            if constexpr (HK == 0) word = __builtin_amdgcn_ubfe(w[j], 5u, pr.flog);  // bits [5, 5 + flog) of the id
+            else word = hash_of<HK>(w[j], pr.fbits) >> 5;
+            fw[j] = (uint32_t)j < gcount ? pr.filt[word] : 0u;
+        }
+        unsigned long long sm[kUnroll];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            uint32_t bit;
+            if constexpr (HK == 0) bit = __builtin_amdgcn_ubfe(fw[j], w[j], 1u);  // the offset takes w's low 5 bits
+            else bit = (fw[j] >> (hash_of<HK>(w[j], pr.fbits) & 31u)) & 1u;
+            sm[j] = __builtin_amdgcn_ballot_w64(bit != 0u) & am[j];
+            tot += (uint32_t)__popcll(sm[j]);
+        }
+        if (tot == 0) return;
+        if (qn + tot > kQueueEntries) flush();
+        if (tot <= kQueueEntries) {
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) append(sm[j], w[j], kk[j]);
+        } else {  // more survivors than the queue holds: chunk by chunk
+#pragma unroll
+            for (int j = 0; j < kUnroll; ++j) {
+                if (qn + (uint32_t)__popcll(sm[j]) > kQueueEntries) flush();
+                append(sm[j], w[j], kk[j]);
+            }
+        }
     };
 
     // Full chunk: every lane active.
     auto fetch = [&](uint32_t& w, uint32_t& kk) {
-        if (__ballot(cur >= end)) {  // uniform test first: most chunks need no lane to advance
-            if (cur >= end) advance();
+        const unsigned long long adv = __builtin_amdgcn_ballot_w64(cur >= end);
+        if (adv) {  // uniform test first: most chunks need no lane to advance
+            if (lane_in(adv)) advance();
         }
         w = load();
         if constexpr (PV) kk = k;
         cur += step;
     };
-    auto probe_group = [&](const uint32_t (&w)[kUnroll], const uint32_t (&kk)[kUnroll]) {
-        uint32_t b[kUnroll];
-        Bucket<S> v[kUnroll];
-#pragma unroll
-        for (int j = 0; j < kUnroll; ++j) {
-            b[j] = hash_of<HK>(w[j], pr.B);
-            v[j] = read_bucket<S>(pr.slots, b[j]);
-        }
-#pragma unroll
-        for (int j = 0; j < kUnroll; ++j) resolve(v[j], w[j], b[j], kk[j], ~0ull);
-    };
+    const unsigned long long all[kUnroll] = {~0ull, ~0ull, ~0ull, ~0ull};
 
     const uint32_t nfull = (hi - lo) >> 6;
     uint32_t c = 0;
@@ -328,16 +399,16 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
         while (c + 2u * kUnroll <= nfull) {
 #pragma unroll
             for (int j = 0; j < kUnroll; ++j) fetch(wb[j], kb[j]);
-            probe_group(wa, ka);
+            filter_group(wa, ka, all, kUnroll);
 #pragma unroll
             for (int j = 0; j < kUnroll; ++j) fetch(wa[j], ka[j]);
-            probe_group(wb, kb);
+            filter_group(wb, kb, all, kUnroll);
             c += 2u * kUnroll;
         }
-        probe_group(wa, ka);
+        filter_group(wa, ka, all, kUnroll);
     }
     // Remaining chunks (leftover full ones, then the ragged last one, whose lanes past hi sit out) in
-    // groups of up to kUnroll: every load of a group is issued before the group is probed.
+    // groups of up to kUnroll: every load of a group is issued before the group is filtered.
     uint32_t left = nfull - c + ((lo + (nfull << 6) < hi) ? 1u : 0u);
     while (left) {
         const uint32_t gcount = left < (uint32_t)kUnroll ? left : (uint32_t)kUnroll;
@@ -364,26 +435,12 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
                 }
             }
         }
-        uint32_t b[kUnroll];
-        Bucket<S> v[kUnroll];
-#pragma unroll
-        for (int j = 0; j < kUnroll; ++j) {
-            if ((uint32_t)j < gcount) {
-                b[j] = hash_of<HK>(w[j], pr.B);
-                v[j] = read_bucket<S>(pr.slots, b[j]);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kUnroll; ++j)
-            if ((uint32_t)j < gcount) resolve(v[j], w[j], b[j], kk[j], am[j]);
+        filter_group(w, kk, am, gcount);
         left -= gcount;
     }
+    if (qn) flush();
     while (pm) step_parked();
-    if constexpr (PV) {
-        if (accn) atomicAdd(&pr.tally[acck], accn);
-        hits += accn;  // hits of u = all v_k tallies: accumulated runs plus parked hits
-    }
-    return wave_sum(hits);
+    return hits;
 }
 
 // The same walk with a per-lane cursor and lane-by-lane chain lookups, for
@@ -476,16 +533,21 @@ struct NoMid {
 template <int S, bool PV, int HK, bool WG, bool DEFER, typename Mid = NoMid, bool SW = false>
 __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t beg, uint32_t d, uint32_t* tbl,
                                         uint64_t avail, int gl, int gsz, int gwave, int gnw, int lane,
-                                        uint32_t* s_wsum, unsigned long long& acc, bool pre = false,
-                                        uint32_t xw = 0, uint32_t xo = 0, uint32_t xl = 0, Mid mid = Mid{},
-                                        uint32_t part = 0, uint32_t parts = 1) {
+                                        uint32_t* s_wsum, unsigned long long& acc, uint32_t* queue,
+                                        bool pre = false, uint32_t xw = 0, uint32_t xo = 0, uint32_t xl = 0,
+                                        Mid mid = Mid{}, uint32_t part = 0, uint32_t parts = 1) {
     gwave = __builtin_amdgcn_readfirstlane(gwave);
-    const Geometry g = geometry_fit(d, S, a.lrecip, PV, (uint32_t)avail);
+    // LDS tables walked by virtual combination carry a filter (the global-memory tables and the
+    // subwave modes look every id up along its chain).
+    constexpr bool FILT = DEFER && !SW;
+    const Geometry g = geometry_fit(d, S, a.lrecip, PV, (uint32_t)avail, FILT);
     uint32_t* slots = tbl;
     uint32_t* len = tbl + g.o_len;
     u32x2* P = reinterpret_cast<u32x2*>(tbl + g.o_P);
     uint32_t* tslot = tbl + g.o_tslot;
     uint32_t* tally = tbl + g.o_tally;
+    uint32_t* filt = tbl + g.o_filt;
+    const uint32_t fwords = g.fbits / 32u;
 
     for (uint32_t x = gl; x < g.B * S; x += gsz) slots[x] = kEmpty;
     for (uint32_t x = gl; x < g.B; x += gsz) len[x] = 0;
@@ -493,9 +555,11 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
         for (uint32_t x = gl; x < g.B * S; x += gsz) tslot[x] = 0;
         for (uint32_t x = gl; x < d; x += gsz) tally[x] = 0;
     }
+    if constexpr (FILT)
+        for (uint32_t x = gl; x < fwords; x += gsz) filt[x] = 0;
     group_sync<WG>();
 
-    // Build the table of N+(u); record each out-neighbour's 2-hop list (length, start).
+    // Build the table of N+(u) (and its filter); record each out-neighbour's 2-hop list (length, start).
     auto insert = [&](uint32_t w) {
         uint32_t b = hash_of<HK>(w, g.B), pos;
         for (;;) {
@@ -504,6 +568,10 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
             b = (b + 1) & g.mask;
         }
         slots[b * S + pos] = w;
+        if constexpr (FILT) {
+            const uint32_t f = hash_of<HK>(w, g.fbits);
+            atomicOr(&filt[f >> 5], 1u << (f & 31u));
+        }
     };
     if (!WG && pre) {
         if ((uint32_t)gl < d) {
@@ -559,7 +627,8 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
     const uint32_t r = part * (uint32_t)gnw + (uint32_t)gwave, rn = parts * (uint32_t)gnw;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * r) / rn));
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)W * (r + 1)) / rn));
-    const Probe pr{a.col, slots, P, tslot, tally, g.B};
+    const Probe pr{a.col, slots, P, tslot, tally, g.B, filt, g.fbits,
+                   fwords ? 31u - (uint32_t)__builtin_clz(fwords) : 0u, queue};
     unsigned long long hits;
     if constexpr (SW) hits = probe_subwave<S, PV, HK>(pr, d, r, rn, a.subwave, lane);
     else hits = probe_range<S, PV, HK, DEFER>(pr, d, lo, hi, lane, a.wide);
@@ -773,13 +842,13 @@ struct AccSink {
 template <int S, bool PV, int HK, bool DEFER, bool SW = false>
 __device__ __forceinline__ void process_wg(const CountArgs& a, uint32_t u, uint32_t* tbl, uint64_t avail, int tid,
                                            int wave, int nw, int lane, uint32_t* s_wsum, unsigned long long& acc,
-                                           uint32_t part = 0, uint32_t parts = 1) {
+                                           uint32_t* queue, uint32_t part = 0, uint32_t parts = 1) {
     u = __builtin_amdgcn_readfirstlane(u);
     if (!in_shard(a, u)) return;
     const int64_t beg = a.off[u];
     const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(a.off[u + 1] - beg));
     process<S, PV, HK, true, DEFER, NoMid, SW>(a, u, beg, d, tbl, avail, tid, blockDim.x, wave, nw, lane, s_wsum, acc,
-                                               false, 0u, 0u, 0u, NoMid{}, part, parts);
+                                               queue, false, 0u, 0u, 0u, NoMid{}, part, parts);
 }
 
 // Tickets of a large-vertex bin of n vertices for `wgs` workgroups: when the bin has fewer vertices
@@ -822,6 +891,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         n_big = a.meta->bins[1];
     }
     if (n_hub + n_big == 0) return;
+    uint32_t* const queue = lds + a.table_words + (size_t)wave * kQueueWords;
     // Item j of bin `bin` (launch-wide index in multi-graph mode) with its graph's arguments.
     auto run = [&](uint32_t bin, uint32_t j, uint32_t* tbl, uint64_t avail, uint32_t part, uint32_t parts, auto wg) {
         if constexpr (MULTI) {
@@ -832,10 +902,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             const CountArgs v = graph_view(a, d);
             sink.to(d.totals, acc, lane);
             process_wg<S, PV, HK, decltype(wg)::value>(v, d.items[bin_base(d.meta, bin) + j - pre[g]], tbl, avail, tid,
-                                                       wave, nw, lane, s_wsum, acc, part, parts);
+                                                       wave, nw, lane, s_wsum, acc, queue, part, parts);
         } else {
             process_wg<S, PV, HK, decltype(wg)::value>(a, a.items[(bin ? n_hub : 0u) + j], tbl, avail, tid, wave, nw,
-                                                       lane, s_wsum, acc, part, parts);
+                                                       lane, s_wsum, acc, queue, part, parts);
         }
     };
 
@@ -891,7 +961,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         n_pack = a.meta->bins[4];
     }
 
-    // Workgroup bin: the table fills the workgroup's LDS.
+    uint32_t* const queue = lds + a.table_words + (size_t)wave * kQueueWords;  // this wavefront's probe queue
+    // Workgroup bin: the table fills the workgroup's table region.
     if (n_wg) {
         for (;;) {
             if (tid == 0) s_item = atomicAdd(&a.heads[2 * kHeadStride], 1u);
@@ -907,10 +978,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 const CountArgs v = graph_view(a, d);
                 sink.to(d.totals, acc, lane);
                 process_wg<S, PV, HK, true, SW>(v, d.items[bin_base(d.meta, 2) + j - pre[g]], lds, a.table_words, tid,
-                                                wave, nw, lane, s_wsum, acc);
+                                                wave, nw, lane, s_wsum, acc, queue);
             } else {
                 process_wg<S, PV, HK, true, SW>(a, a.items[n_before + j], lds, a.table_words, tid, wave, nw, lane,
-                                                s_wsum, acc);
+                                                s_wsum, acc, queue);
             }
         }
     }
@@ -1005,8 +1076,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 };
                 if (in_shard(v, u))
                     process<S, PV, HK, false, true, decltype(mid), SW>(v, u, beg, d, slice, a.slice_words, lane,
-                                                                       64, 0, 1, lane, nullptr, acc, d <= 64u, xw,
-                                                                       xo, xl, mid);
+                                                                       64, 0, 1, lane, nullptr, acc, queue, d <= 64u,
+                                                                       xw, xo, xl, mid);
                 else
                     mid();
                 xw = nw;

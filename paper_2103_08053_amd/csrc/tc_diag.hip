@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_collisions(DiagArgs a) {
         const uint32_t u = a.items[j];
         const int64_t beg = a.off[u];
         const uint32_t d = (uint32_t)(a.off[u + 1] - beg);
-        const Geometry g = geometry_fit(d, a.S, a.lrecip, a.pv != 0, a.avail[bin]);
+        const Geometry g = geometry_fit(d, a.S, a.lrecip, a.pv != 0, a.avail[bin], a.filt[bin] != 0);
         if (threadIdx.x == 0) { s_w = 0; s_max = 0; }
         __syncthreads();
         unsigned long long w_part = 0;

@@ -41,12 +41,22 @@ static_assert(sizeof(GraphMeta) == 256, "meta is one 256-byte block");
 // Hash-table geometry for a vertex with d out-neighbours, shared by the host
 // (capacity per bin) and the kernels (layout in LDS or in global memory).
 // Layout in 32-bit words:
-//   slots[B*S] | len[B] | pad to 4 | P[2d] | (per-vertex mode) tslot[B*S] | tally[d]
+//   slots[B*S] | len[B] | pad to 4 | P[2d] | (per-vertex mode) tslot[B*S] | tally[d] | pad to 4 |
+//   (filtered tables) filt[fw]
 // B is the smallest power of two with B*S > d and B*S*load >= d, so every
-// probe chain ends at a bucket with a free slot.
+// probe chain ends at a bucket with a free slot.  filt is a bit vector of 32*fw
+// bits (a power of two) with bit hash(w) set for every element w: a probe whose
+// bit is clear cannot be in the table and skips the bucket lookup.
 struct Geometry {
-    uint32_t B, mask, o_len, o_P, o_tslot, o_tally, words;
+    uint32_t B, mask, o_len, o_P, o_tslot, o_tally, o_filt, fbits, words;
 };
+
+// A wavefront's queue of probes that passed the filter, at the end of each count launch's LDS:
+// kQueueEntries entries of two words (the probed id and, in per-vertex mode, its out-neighbour
+// index), then one two-word dummy entry per lane (lanes without a survivor write there, so the
+// appends need no lane mask).
+constexpr uint32_t kQueueEntries = 64;
+constexpr uint32_t kQueueWords = 2 * (kQueueEntries + 64);
 
 // Bucket of element w in a table of B (power of two) buckets: kind 0 takes the low bits of the id
 // (ids are degree ranks), kind 1 a multiplicative (Fibonacci) hash.
@@ -64,8 +74,13 @@ __host__ __device__ inline uint32_t pow2_floor(uint32_t x) { return x ? 1u << (3
 // Host and device size tables from this same value, so a vertex binned by the host fits on the device.
 __host__ __device__ inline uint32_t load_recip(uint32_t load_pct) { return (100u * 65536u + load_pct - 1) / load_pct; }
 
-// Layout for d elements in B buckets.
-__host__ __device__ inline Geometry geometry_b(uint32_t d, uint32_t S, uint32_t B, bool pv) {
+// Filter words for d elements: at least 16 bits per element (at most 1/16 of the bits set, so at
+// most about 6% of the probes that miss pass the filter), at most 64.
+__host__ __device__ inline uint32_t filter_words_min(uint32_t d) { return pow2_ceil(d) > 2u ? pow2_ceil(d) / 2u : 1u; }
+__host__ __device__ inline uint32_t filter_words_max(uint32_t d) { return 2u * pow2_ceil(d); }
+
+// Layout for d elements in B buckets with a filter of fw words (0: none).
+__host__ __device__ inline Geometry geometry_b(uint32_t d, uint32_t S, uint32_t B, bool pv, uint32_t fw = 0) {
     Geometry g;
     g.B = B;
     g.mask = B - 1;
@@ -73,26 +88,40 @@ __host__ __device__ inline Geometry geometry_b(uint32_t d, uint32_t S, uint32_t 
     g.o_P = (g.o_len + B + 3u) & ~3u;
     g.o_tslot = g.o_P + 2 * d;
     g.o_tally = g.o_tslot + (pv ? B * S : 0);
-    g.words = (g.o_tally + (pv ? d : 0) + 3u) & ~3u;
+    g.o_filt = (g.o_tally + (pv ? d : 0) + 3u) & ~3u;
+    g.fbits = 32u * fw;
+    g.words = (g.o_filt + fw + 3u) & ~3u;
     return g;
 }
 
 // The smallest table the load factor allows (used to decide which bin a vertex fits):
-// B*S > d and B*S >= d * 100 / load (lrecip = load_recip(load)).
-__host__ __device__ inline Geometry geometry(uint32_t d, uint32_t S, uint32_t lrecip, bool pv) {
+// B*S > d and B*S >= d * 100 / load (lrecip = load_recip(load)); with `filt`, the smallest filter.
+__host__ __device__ inline Geometry geometry(uint32_t d, uint32_t S, uint32_t lrecip, bool pv, bool filt = false) {
     uint32_t need = d / S + 1;
     const uint64_t slots = ((uint64_t)d * lrecip + 65535u) >> 16;
     const uint32_t c = (uint32_t)((slots + S - 1) / S);
     if (c > need) need = c;
-    return geometry_b(d, S, pow2_ceil(need), pv);
+    return geometry_b(d, S, pow2_ceil(need), pv, filt ? filter_words_min(d) : 0u);
 }
 
-// The table actually used: the largest power-of-two B at least the minimal one that fits `avail`
-// words and holds at most max(64, 8 d) slots, so a vertex whose region has room gets a lightly loaded
-// table (fewer full buckets to walk).  words(B) <= B (S (1 + pv) + 1) + (2 + pv) d + 8 bounds the
-// layout, which gives B in closed form.
-__host__ __device__ inline Geometry geometry_fit(uint32_t d, uint32_t S, uint32_t lrecip, bool pv, uint32_t avail) {
-    const Geometry g = geometry(d, S, lrecip, pv);
+// The table actually used in a region of `avail` words (at least the minimal geometry).
+// Filtered tables (the LDS tables probed through the filter) keep the minimal B and give the room
+// to the filter: the largest power-of-two filter up to 64 bits per element.  Unfiltered tables
+// take the largest power-of-two B at least the minimal one that fits and holds at most
+// max(64, 8 d) slots, so a vertex whose region has room gets a lightly loaded table (fewer full
+// buckets to walk); words(B) <= B (S (1 + pv) + 1) + (2 + pv) d + 8 bounds that layout, which gives
+// B in closed form.
+__host__ __device__ inline Geometry geometry_fit(uint32_t d, uint32_t S, uint32_t lrecip, bool pv, uint32_t avail,
+                                                 bool filt = false) {
+    const Geometry g = geometry(d, S, lrecip, pv, filt);
+    if (filt) {
+        const uint32_t room = avail > g.o_filt ? avail - g.o_filt : 0u;
+        uint32_t fw = room >= 4u ? pow2_floor(room) : 0u;  // a power of two >= 4 needs no padding
+        const uint32_t fmax = filter_words_max(d);
+        if (fw > fmax) fw = fmax;
+        if (fw <= g.fbits / 32u) return g;
+        return geometry_b(d, S, g.B, pv, fw);
+    }
     const uint32_t cap_slots = d > 8u ? 8u * d : 64u;
     uint32_t B = pow2_floor(cap_slots / S);
     const uint32_t fixed = (pv ? 3u : 2u) * d + 8u;
@@ -127,12 +156,12 @@ __host__ __device__ inline bool wide_list_addressing(uint64_t m_in, bool forced)
 }
 
 // Largest d whose table fits in `words` 32-bit words (0 if none).
-inline uint32_t capacity(uint32_t words, uint32_t S, uint32_t load_pct, bool pv) {
+inline uint32_t capacity(uint32_t words, uint32_t S, uint32_t load_pct, bool pv, bool filt = false) {
     const uint32_t lr = load_recip(load_pct);
     uint32_t lo = 0, hi = words;  // words(d) >= 2d, so d <= words / 2
     while (lo < hi) {
         uint32_t mid = lo + (hi - lo + 1) / 2;
-        if (geometry(mid, S, lr, pv).words <= words) lo = mid; else hi = mid - 1;
+        if (geometry(mid, S, lr, pv, filt).words <= words) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -246,7 +275,8 @@ struct CountArgs {
     unsigned long long hub_words;
     uint32_t hub_wgs;                // workgroups of the large-table launch that take global-table vertices
     uint32_t slice_words;            // per-wavefront LDS slice
-    uint32_t table_words;            // LDS words of the workgroup table region (of this launch)
+    uint32_t table_words;            // LDS words of the workgroup table region (of this launch); the
+                                     // wavefronts' probe queues (kQueueWords each) follow it
     uint32_t lrecip;                 // load_recip(load factor)
     uint32_t chunk;
     uint32_t pack_region;            // LDS words of a packed vertex's table (a quarter of a wavefront slice)
@@ -273,6 +303,7 @@ struct DiagArgs {
     const uint32_t* col;
     const uint32_t* items;
     uint32_t avail[5];
+    uint32_t filt[5];                // whether the count's tables of each bin carry a filter
     uint32_t S, lrecip, hash_kind, pv;
     unsigned long long* stats;
 };

@@ -63,7 +63,7 @@ def test_single_graph_batch(ctx):
     assert totals[0] == ctx.count(g.src, g.dst, g.n)[0]
 
 
-@pytest.mark.parametrize("kw", [dict(flags=2), dict(flags=4), dict(flags=32), dict(wg_lds_bytes=4096, wg_waves=4),
+@pytest.mark.parametrize("kw", [dict(flags=2), dict(flags=4), dict(flags=32), dict(wg_lds_bytes=4096, wg_waves=2),
                                 dict(slots_per_bucket=1, load_factor_pct=100), dict(hash_kind=1),
                                 dict(flags=0x40), dict(flags=0x80), dict(flags=0x200)],
                          ids=["wg", "hub", "big", "tinylds", "s1full", "hash1", "order_in", "order_collective",

@@ -103,7 +103,7 @@ def test_count_graphs_with_batch_handles(ctx):
         assert (pvb[batch.voff[i]:batch.voff[i + 1]] == ref(g).per_vertex).all(), g.name
 
 
-@pytest.mark.parametrize("kw", [dict(flags=2), dict(flags=4), dict(flags=32), dict(wg_lds_bytes=4096, wg_waves=4),
+@pytest.mark.parametrize("kw", [dict(flags=2), dict(flags=4), dict(flags=32), dict(wg_lds_bytes=4096, wg_waves=2),
                                 dict(slots_per_bucket=1, load_factor_pct=100), dict(hash_kind=1),
                                 dict(flags=0x40), dict(flags=0x1000), dict(light_chunk=1), dict(grid_wgs=3),
                                 dict(flags=0x10)],

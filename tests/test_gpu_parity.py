@@ -110,7 +110,7 @@ FORCED = [
     dict(flags=0x80 | 4, slots_per_bucket=1, load_factor_pct=100),
     dict(flags=0x100), dict(flags=0x200), dict(flags=0x400), dict(flags=0x800),   # subwave / per-wave lists
     dict(flags=0x100 | 4), dict(flags=0x200 | 32), dict(flags=0x400 | 2, slots_per_bucket=1, load_factor_pct=100),
-    dict(wg_lds_bytes=4096, wg_waves=4),        # tiny LDS: most vertices spill to the global-table bin
+    dict(wg_lds_bytes=4096, wg_waves=2),        # tiny LDS: most vertices spill to the global-table bin
     dict(slots_per_bucket=1), dict(slots_per_bucket=4),
     dict(load_factor_pct=100), dict(load_factor_pct=10),
     dict(slots_per_bucket=1, load_factor_pct=100, flags=2),   # long probe chains in LDS
@@ -147,7 +147,7 @@ def test_bins_are_exercised(torch):
     info = Context(0, Params(wave_max_dplus=32)).build(g.src, g.dst, g.n).info()
     assert info.n_wg > 0 and info.n_wave > 0 and info.n_hub == 0 and info.n_big == 0
     assert info.big_cap > info.wg_cap
-    c = Context(0, Params(wg_lds_bytes=4096, wg_waves=4))
+    c = Context(0, Params(wg_lds_bytes=4096, wg_waves=2))
     small = c.build(g.src, g.dst, g.n).info()
     assert small.n_big > 0 and small.n_hub == 0
     assert_parity(c, g)
@@ -309,7 +309,7 @@ def test_shards_sum_to_whole(ctx, torch, shards):
 def test_shards_batch_and_forced_paths(torch):
     from paper_2103_08053_amd import Batch, Context, Params
     gs = [gg.complete(40), gg.wheel(60), gg.dirty(gg.rmat(11, 16, seed=2), seed=3), gg.friendship(30)]
-    for kw in (dict(), dict(flags=4), dict(flags=32), dict(wg_lds_bytes=4096, wg_waves=4)):
+    for kw in (dict(), dict(flags=4), dict(flags=32), dict(wg_lds_bytes=4096, wg_waves=2)):
         c = Context(0, Params(**kw))
         b = Batch(c, [(g.n, g.src, g.dst) for g in gs])
         whole = b.count()[0]
@@ -332,18 +332,22 @@ def test_shard_arguments_checked(ctx, torch):
 # ----------------------------------------------------------------------------- collision statistics
 
 def test_collision_stats_complete_graph(ctx, torch):
-    """K_100: N+(u) is a run of consecutive ranks and (default knobs without the packed bin's
-    quarter-slice tables, d+ < 100) every table has B >= d+ buckets, so with the low-bits hash no
-    two out-neighbours share a home bucket: max collision 1 everywhere and phi (Equation 2) = W+."""
+    """K_100: N+(u) is a run of d+ consecutive ranks.  With default knobs and no packed bin every
+    table (d+ < 100) is a wavefront table with a filter, which keeps the load-factor bucket count:
+    B = the power of two >= d+/2, so B < d+ <= 2B and d+ consecutive ids under the low-bits hash put
+    exactly two out-neighbours in some home bucket and never three: max collision 2 everywhere and
+    phi (Equation 2) = 2 W+."""
     from paper_2103_08053_amd import Context, Params
     g = gg.complete(100)
-    graph = Context(0, Params(flags=0x1000)).build(g.src, g.dst, g.n)
-    info = graph.info()
-    for pv in (True, False):
-        st = graph.collisions(per_vertex=pv)
-        assert st["tables"] == g.n - 2 == info.n_wave + info.n_wg + info.n_big + info.n_hub + info.n_packed
-        assert st["max_collision"] == 1 and st["sum_max_collision"] == st["tables"]
-        assert st["phi"] == info.wedges_plus
+    for flags, mc in ((0x1000, 2),):
+        graph = Context(0, Params(flags=flags)).build(g.src, g.dst, g.n)
+        info = graph.info()
+        assert info.n_wave == g.n - 2
+        for pv in (True, False):
+            st = graph.collisions(per_vertex=pv)
+            assert st["tables"] == g.n - 2 == info.n_wave + info.n_wg + info.n_big + info.n_hub + info.n_packed
+            assert st["max_collision"] == mc and st["sum_max_collision"] == mc * st["tables"], (flags, pv, st)
+            assert st["phi"] == mc * info.wedges_plus
 
 
 def test_collision_stats_bounds(torch):
@@ -387,7 +391,7 @@ def test_plain_vertex_and_edge_centric_designs(ctx, torch, g):
 
 def test_plain_designs_reject_what_they_cannot_hold(torch):
     from paper_2103_08053_amd import Batch, Context, Params, TCError
-    c = Context(0, Params(wg_lds_bytes=4096, wg_waves=4))
+    c = Context(0, Params(wg_lds_bytes=4096, wg_waves=2))
     g = gg.complete(9000)  # d+ up to 8999: beyond any LDS table
     graph = c.build(g.src, g.dst, g.n)
     with pytest.raises(TCError):
@@ -406,7 +410,7 @@ def test_packed_light_vertices_match_unpacked(torch):
     gs = [gg.dirty(gg.erdos_renyi(5000, 40000, seed=3), seed=4), gg.erdos_renyi(20000, 320000, seed=5),
           gg.barabasi_albert(4000, 6, seed=6), gg.complete(20), gg.cycle(50), gg.torus3d(7)]
     for kw in (dict(), dict(flags=0x1000), dict(load_factor_pct=10), dict(slots_per_bucket=1, load_factor_pct=100),
-               dict(wg_lds_bytes=8192), dict(hash_kind=1), dict(flags=0x40)):
+               dict(wg_lds_bytes=8192, wg_waves=4), dict(hash_kind=1), dict(flags=0x40)):
         c = Context(0, Params(**kw))
         if not kw:
             info = c.build(gs[1].src, gs[1].dst, gs[1].n).info()
@@ -425,7 +429,7 @@ def test_bin_work_sums_to_wedges(ctx, torch):
     from paper_2103_08053_amd import Context, Params
     g = gg.dirty(gg.rmat(14, 16, seed=9), seed=10)
     r = oracle.count(g.n, g.src, g.dst)
-    for kw in (dict(), dict(wave_max_dplus=32), dict(wg_lds_bytes=4096, wg_waves=4), dict(flags=4)):
+    for kw in (dict(), dict(wave_max_dplus=32), dict(wg_lds_bytes=4096, wg_waves=2), dict(flags=4)):
         graph = Context(0, Params(**kw)).build(g.src, g.dst, g.n)
         info, work = graph.info(), graph.bin_work()
         assert sum(work) == r.wedges_plus == info.wedges_plus, kw

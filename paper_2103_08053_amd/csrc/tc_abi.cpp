@@ -155,19 +155,21 @@ tc_status check_params(const tc_params* p) {
     return TC_OK;
 }
 
-// LDS words of the main launch's table region: its LDS minus the wavefronts' probe queues.
+// LDS of the main launch.  While its workgroups take workgroup-bin vertices, the table region is
+// the LDS minus the wavefronts' probe queues at its end; afterwards every wavefront owns a region
+// of its own (1/wg_waves of the LDS): a table slice followed by its probe queue, or four
+// packed-vertex tables (which need no queue).
 uint32_t wg_table_words(const tc_params& p) { return p.wg_lds_bytes / 4 - p.wg_waves * tc::kQueueWords; }
 
-// A wavefront's slice of the table region.
-uint32_t slice_words(const tc_params& p) {
-    return (wg_table_words(p) / p.wg_waves) & ~3u;
-}
+// A wavefront's region, and the table slice at its start.
+uint32_t wave_region_words(const tc_params& p) { return (p.wg_lds_bytes / 4 / p.wg_waves) & ~3u; }
+uint32_t slice_words(const tc_params& p) { return wave_region_words(p) - tc::kQueueWords; }
 
 // Table region of the large-vertex launch (16 wavefronts, all the LDS a workgroup may have).
 uint32_t big_table_words(const tc_context* ctx) { return ctx->big_lds_bytes / 4 - tc::kMaxWaves * tc::kQueueWords; }
 
 // LDS words of a packed light vertex's table: a quarter of a wavefront slice.
-uint32_t pack_region(const tc_params& p) { return (slice_words(p) / 4) & ~3u; }
+uint32_t pack_region(const tc_params& p) { return (wave_region_words(p) / 4) & ~3u; }
 
 tc::BinCaps bin_caps(const tc_context* ctx, const tc_params& p) {
     tc::BinCaps c{};

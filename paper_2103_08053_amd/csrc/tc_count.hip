@@ -310,8 +310,9 @@ __device__ __forceinline__ unsigned long long probe_range_lds(const Probe& pr, u
             if (hit) tally_slot4<S>(pr, b, bucket_pos4<S>(v, w));
             // tally[k] += hits of each run of equal k: the run's last lane adds the hits up to and
             // including it, the run's first lane subtracts the hits below it (modulo 2^32).
-            const uint32_t kprev = (uint32_t)__shfl_up((int)kk, 1, 64);
-            const uint32_t knext = (uint32_t)__shfl_down((int)kk, 1, 64);
+            // k of the lanes below and above (wave_shr:1 / wave_shl:1 lane moves; the end lanes get ~0)
+            const uint32_t kprev = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)kk, 0x138, 0xf, 0xf, false);
+            const uint32_t knext = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)kk, 0x130, 0xf, 0xf, false);
             const uint32_t below = lanes_below(hm);
             const bool first = act && (lane == 0 || kprev != kk);
             const bool last = act && ((uint32_t)lane + 1u == qn || knext != kk);
@@ -993,7 +994,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     // moves on when its sub-queue is drained, and requests its next chunk before working on the
     // current one.  `work(args, base, j0, j1)` processes items base + [j0, j1) of the bin with the
     // arguments of their graph (in multi-graph mode a chunk never spans two graphs).
-    uint32_t* slice = lds + (size_t)wave * a.slice_words;
+    // The wavefront's own region (after the workgroup bin): a table slice and its probe queue, or
+    // four packed-vertex tables.
+    uint32_t* slice = lds + (size_t)wave * (a.slice_words + kQueueWords);
+    uint32_t* const slice_queue = slice + a.slice_words;
     auto drain = [&](uint32_t bin, uint32_t n_bin, uint32_t base1, uint32_t per_fetch, uint32_t head0,
                      auto&& work) {
         const uint32_t nchunks = MULTI ? a.multi->fetch_tot[bin] : (n_bin + per_fetch - 1) / per_fetch;
@@ -1076,7 +1080,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 };
                 if (in_shard(v, u))
                     process<S, PV, HK, false, true, decltype(mid), SW>(v, u, beg, d, slice, a.slice_words, lane,
-                                                                       64, 0, 1, lane, nullptr, acc, queue, d <= 64u,
+                                                                       64, 0, 1, lane, nullptr, acc, slice_queue,
+                                                                       d <= 64u,
                                                                        xw, xo, xl, mid);
                 else
                     mid();

@@ -274,7 +274,8 @@ struct CountArgs {
     uint32_t* hub_scratch;           // hub_wgs * hub_words words
     unsigned long long hub_words;
     uint32_t hub_wgs;                // workgroups of the large-table launch that take global-table vertices
-    uint32_t slice_words;            // per-wavefront LDS slice
+    uint32_t slice_words;            // per-wavefront LDS table slice (each wavefront region: the slice,
+                                     // then its probe queue of kQueueWords)
     uint32_t table_words;            // LDS words of the workgroup table region (of this launch); the
                                      // wavefronts' probe queues (kQueueWords each) follow it
     uint32_t lrecip;                 // load_recip(load factor)

@@ -128,8 +128,8 @@ def issue_ceiling(per_vertex: bool, workload: str, kernel_ms: float):
 
 
 def copy_calibration():
-    """A plain device-to-device copy of known size (read CALIB_BYTES, write
-    CALIB_BYTES), so FETCH_SIZE / WRITE_SIZE can be scaled to bytes."""
+    """A plain device-to-device copy of known size (read CALIB_BYTES, write CALIB_BYTES), run first
+    so the byte counters of a profile can be checked against a known traffic."""
     import torch
     a = torch.empty(CALIB_BYTES, dtype=torch.uint8, device="cuda:0")
     b = torch.empty_like(a)
@@ -608,8 +608,9 @@ def main():
         "build_ms": float(np.mean(build_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_vertex, args.workload),
-                     "traffic_kind": "bytes between the L2 and the memory fabric (FETCH_SIZE + WRITE_SIZE scaled "
-                                     "by a device copy); Infinity Cache hits included, so not DRAM bytes",
+                     "traffic_kind": "bytes between the L2 and the memory fabric per launch, from request counters "
+                                     "resolved by size (32/64/128-byte reads, 32/64-byte writes); Infinity Cache "
+                                     "hits included, so not DRAM bytes",
                      "achieved_kind": "algorithmic bytes / kernel time (no cache reuse assumed: re-reads served "
                                       "by the L2 or the Infinity Cache count as if they came from HBM)",
                      "kernel": "tc_count_kernel (after tc_hub_kernel, both inside the events)",

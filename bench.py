@@ -421,9 +421,9 @@ def run_serve(args):
     sweep = []
     if args.sweep:
         for rate in [float(x) for x in args.sweep.split(",")]:
-            sweep.append(serve_once(args, pool, want, rate, 2.0, args.sweep_window, "each", seed=13))
+            sweep.append(serve_once(args, pool, want, rate, 2.0, args.sweep_window, args.sweep_mode, seed=13))
     ok = [s["rate"] for s in sweep if s["p99_ms"] <= args.p99_bound_ms and s["unanswered"] == 0]
-    main = res.get("each") or next(iter(res.values()))
+    main = res.get("union") or next(iter(res.values()))
     out = {
         "metric": "served requests: p50/p99 latency and throughput, continuous batching vs plain FIFO",
         "value": main["throughput_rps"], "unit": "requests/s", "n_gpus": 1, "steps": main["requests"],
@@ -459,10 +459,12 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=30.0, help="serving: measured window (s)")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="serving: warm-up before the window (s)")
-    ap.add_argument("--serve-modes", default="each,union,fifo",
-                    help="serving: each (build on arrival + tc_count_graphs), union (batch build), fifo (plain)")
+    ap.add_argument("--serve-modes", default="union,each,fifo",
+                    help="serving: union (each count's requests built as one union, counted by a replayed "
+                         "tc_count_graphs), each (every request built on arrival, counted together), fifo (plain)")
     ap.add_argument("--sweep", default="", help="serving: comma-separated rates for the sustainable-rate search")
     ap.add_argument("--sweep-window", type=float, default=8.0)
+    ap.add_argument("--sweep-mode", default="union", help="serving: the server the rate sweep runs")
     ap.add_argument("--p99-bound-ms", type=float, default=100.0)
     ap.add_argument("--serve-max-scale", type=int, default=20)
     ap.add_argument("--hbm-budget-gb", type=int, default=96)

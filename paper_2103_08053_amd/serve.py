@@ -4,24 +4,27 @@ Requests (graphs as edge lists in pinned host memory) arrive over time.  The
 loop, on one host thread:
 
 * admits waiting requests first come first served while their device
-  footprint (built-graph storage and the edge list copy, from the library's
-  size queries) fits the free HBM budget;
-* builds every admitted request on its own as soon as it is admitted
-  (tc_graph_build: clean, orient, bin) on the *build* stream, so a request's
-  preprocessing starts at once and overlaps the counts already running;
-* whenever fewer than `max_inflight` counts are on the device, counts all
-  built-or-building requests (up to `max_batch`) with ONE tc_count_graphs
-  call on the *count* stream, replayed from a HIP graph captured once per
-  workspace (the launches read k and the graph descriptors from the
-  workspace), followed by an asynchronous copy of the totals to pinned host
-  memory;
+  footprint (storage, build memory and the edge list copy, from the
+  library's size queries) fits the free HBM budget and the count has fewer
+  than `max_batch` requests;
+* whenever fewer than `max_inflight` counts are on the device, copies the
+  admitted requests to the device and builds them on the *build* stream as
+  one disjoint union (tc_batch_build: one set of preprocessing launches for
+  all of them), then counts them on the *count* stream with ONE
+  tc_count_graphs call replayed from a HIP graph captured once per workspace
+  (the launches read k and the graph descriptors from the workspace),
+  followed by an asynchronous copy of the totals to pinned host memory; so
+  requests that arrive while others are on the GPU join the next count, and
+  its build overlaps the counts ahead of it;
 * retires a count when its event has completed: every request in it is
   answered and its device memory returns to the budget;
 * when the device is idle and exactly one request waits, answers it directly
   through tc_count (no pipeline set-up), unless ``direct_when_idle`` is off.
 
-With ``build="union"`` the admitted requests of a count are instead built
-together as one disjoint union (tc_batch_build) right before it.
+With ``build="each"`` every request is instead built on its own as soon as it
+is admitted (tc_graph_build), and all built or building requests are counted
+together: a request's preprocessing starts earlier, but each build pays its
+own ~35 launches, which caps the rate (measured below the union server's).
 
 Latency of a request = time its answer is available on the host - its
 scheduled arrival time.  :func:`serve_fifo` is the plain baseline: one
@@ -78,7 +81,7 @@ def make_request(rid: int, n: int, src, dst) -> Request:
 
 class Server:
     def __init__(self, device: int = 0, params: Params | None = None, hbm_budget: int = 64 << 30,
-                 max_batch: int = 256, max_inflight: int = 2, direct_when_idle: bool = True, build: str = "each"):
+                 max_batch: int = 256, max_inflight: int = 2, direct_when_idle: bool = True, build: str = "union"):
         import torch
         if build not in ("each", "union"):
             raise ValueError("build is 'each' or 'union'")

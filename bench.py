@@ -599,8 +599,9 @@ def main():
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "m_in": g.m_in, "m": info.m, "wedges_plus": info.wedges_plus,
                    "max_dplus": info.max_dplus, "per_vertex": per_vertex, "triangles": total,
-                   "bins": {"global_table": info.n_hub, "large_lds": info.n_big, "workgroup": info.n_wg,
-                            "wavefront": info.n_wave},
+                   "bins": {"global_table": info.n_hub, "large_lds": info.n_big,
+                            "large_lds_half": info.n_mid, "workgroup": info.n_wg, "wavefront": info.n_wave,
+                            "packed": info.n_packed},
                    "params": vars(ctx.params)},
         "count_kernel_ms": kernel_ms,
         "count_kernel_median_ms": kernel_median_ms,

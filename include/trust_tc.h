@@ -89,6 +89,9 @@ typedef struct tc_params {
                                     with out-degree <= 32 and W(u) <= 512 are at least half of the
                                     wavefront-size tables, they share wavefronts, 4 x 16 lanes when
                                     out-degrees are <= 16, else 2 x 32 lanes) */
+#define TC_F_NO_MID      0x2000u /* every large-LDS-bin vertex in the full-LDS launch (one workgroup per
+                                    CU); default: those whose tables fit half a CU's LDS are counted by a
+                                    second launch with two workgroups per CU */
 
 /* Opaque handles. */
 typedef struct tc_context tc_context;
@@ -109,6 +112,9 @@ typedef struct tc_graph_info {
     uint32_t big_cap;     /* out-degree limit of the large-LDS bin */
     uint32_t n_packed;    /* light vertices (out-degree <= 32, W(u) <= 512) packed 2-4 to a wavefront; only
                              when they are at least half of the wavefront-size tables */
+    uint32_t n_mid;       /* vertices of the large-LDS bin (counted in n_big) whose tables fit half a CU's
+                             LDS: a second launch counts them with two workgroups per CU */
+    uint32_t mid_cap;     /* out-degree limit of that part (0: no such launch) */
     uint32_t reserved;
 } tc_graph_info;
 

@@ -24,6 +24,7 @@ struct tc_context {
     int cu_count = 0;
     size_t lds_per_block_max = 0;
     uint32_t big_lds_bytes = 0;  // dynamic LDS of the large-vertex kernel: all a workgroup may have
+    uint32_t mid_lds_bytes = 0;  // the same kernel with two workgroups per CU: half a CU's LDS (0: unknown)
     tc_params p{};
     std::string err;
     bool timing = false;
@@ -148,7 +149,8 @@ tc_status check_params(const tc_params* p) {
     if (p->hash_kind > 1) return TC_E_INVALID;
     if (p->light_chunk < 1 || p->light_chunk > 256) return TC_E_INVALID;
     if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SCATTER_CSR | TC_F_WIDE_ADDR |
-                     TC_F_FORCE_BIG | TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE | kIntraFlags | TC_F_NO_PACK))
+                     TC_F_FORCE_BIG | TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE | kIntraFlags | TC_F_NO_PACK |
+                     TC_F_NO_MID))
         return TC_E_INVALID;
     if (__builtin_popcount(p->flags & kIntraFlags) > 1) return TC_E_INVALID;
     if ((p->flags & TC_F_ORDER_INDEGREE) && (p->flags & TC_F_ORDER_COLLECTIVE)) return TC_E_INVALID;
@@ -165,8 +167,13 @@ uint32_t wg_table_words(const tc_params& p) { return p.wg_lds_bytes / 4 - p.wg_w
 uint32_t wave_region_words(const tc_params& p) { return (p.wg_lds_bytes / 4 / p.wg_waves) & ~3u; }
 uint32_t slice_words(const tc_params& p) { return wave_region_words(p) - tc::kQueueWords; }
 
-// Table region of the large-vertex launch (16 wavefronts, all the LDS a workgroup may have).
+// Table region of the large-vertex launch (16 wavefronts, all the LDS a workgroup may have), and of
+// its half-LDS launch (two such workgroups per CU).
 uint32_t big_table_words(const tc_context* ctx) { return ctx->big_lds_bytes / 4 - tc::kMaxWaves * tc::kQueueWords; }
+uint32_t mid_table_words(const tc_context* ctx) {
+    const uint32_t q = tc::kMidWaves * tc::kQueueWords;
+    return ctx->mid_lds_bytes / 4 > q ? ctx->mid_lds_bytes / 4 - q : 0u;
+}
 
 // LDS words of a packed light vertex's table: a quarter of a wavefront slice.
 uint32_t pack_region(const tc_params& p) { return (wave_region_words(p) / 4) & ~3u; }
@@ -181,6 +188,13 @@ tc::BinCaps bin_caps(const tc_context* ctx, const tc_params& p) {
     if (p.wave_max_dplus && p.wave_max_dplus < c.wave_cap) c.wave_cap = p.wave_max_dplus;
     c.big_cap = tc::capacity(big_table_words(ctx), p.slots_per_bucket, p.load_factor_pct, true, true);
     if (c.big_cap < c.wg_cap) c.big_cap = c.wg_cap;
+    // Half-LDS part of bin 1: out-degrees above the workgroup bin whose tables fit half a CU's LDS
+    // (not when a forced bin asks for the full-LDS path).
+    c.mid_cap = 0;
+    if (!(p.flags & (TC_F_NO_MID | TC_F_FORCE_BIG | TC_F_FORCE_HUB | TC_F_FORCE_WG)) && mid_table_words(ctx)) {
+        const uint32_t mc = tc::capacity(mid_table_words(ctx), p.slots_per_bucket, p.load_factor_pct, true, true);
+        if (mc > c.wg_cap && mc < c.big_cap) c.mid_cap = mc;
+    }
     c.force_wg = (p.flags & TC_F_FORCE_WG) != 0;
     c.force_hub = (p.flags & TC_F_FORCE_HUB) != 0;
     c.force_big = (p.flags & TC_F_FORCE_BIG) != 0;
@@ -336,8 +350,10 @@ uint32_t launch_lds(const tc_context* ctx, const tc_params& p, bool hub) {
     return hub ? ctx->big_lds_bytes : p.wg_lds_bytes;
 }
 
-tc_status occupancy(tc_context* ctx, const tc_params& p, bool pv, bool hub, int* per_cu, bool multi = false) {
-    const uint32_t threads = launch_threads(p, hub), lds = launch_lds(ctx, p, hub);
+tc_status occupancy(tc_context* ctx, const tc_params& p, bool pv, bool hub, int* per_cu, bool multi = false,
+                    uint32_t lds_bytes = 0, uint32_t threads_override = 0) {
+    const uint32_t threads = threads_override ? threads_override : launch_threads(p, hub);
+    const uint32_t lds = lds_bytes ? lds_bytes : launch_lds(ctx, p, hub);
     const uint32_t sw = (!hub && !multi && subwave_lanes(p.flags)) ? 1u : 0u;
     const uint32_t mu = multi ? 1u : 0u;
     for (const auto& o : ctx->occ)
@@ -396,12 +412,16 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.subwave = subwave_lanes(p.flags);
     a.pack_region = pack_region(p);
     const bool hub = needs_hub_launch(g);
-    int per_cu = 0, per_cu_hub = 0;
+    int per_cu = 0, per_cu_hub = 0, per_cu_mid = 0;
     if (tc_status st = occupancy(ctx, p, pv, false, &per_cu)) return st;
     if (hub)
         if (tc_status st = occupancy(ctx, p, pv, true, &per_cu_hub)) return st;
+    if (hub && g->caps.mid_cap)
+        if (tc_status st = occupancy(ctx, p, pv, true, &per_cu_mid, false, ctx->mid_lds_bytes, 64 * tc::kMidWaves))
+            return st;
     const uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu * ctx->cu_count);
     const uint32_t grid_hub = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu_hub * ctx->cu_count);
+    const uint32_t grid_mid = p.grid_wgs ? p.grid_wgs : (uint32_t)(per_cu_mid * ctx->cu_count);
     if (grid_hub < a.hub_wgs) a.hub_wgs = grid_hub;
     HIP_TRY(ctx, tc::fill_u32(a.heads, 0, tc::kHeadWords, s));
     HIP_TRY(ctx, tc::fill_u32(d_totals, 0, 2 * (size_t)g->k, s));
@@ -410,8 +430,16 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
     if (hub) {
         a.table_words = big_table_words(ctx);
+        a.hub_part = 0;
         HIP_TRY(ctx, tc::count_launch(true, false, p.slots_per_bucket, pv, p.hash_kind, grid_hub, launch_threads(p, true),
                                       launch_lds(ctx, p, true), a, s));
+        if (g->caps.mid_cap) {
+            a.table_words = mid_table_words(ctx);
+            a.hub_part = 1;
+            HIP_TRY(ctx, tc::count_launch(true, false, p.slots_per_bucket, pv, p.hash_kind, grid_mid,
+                                          64 * tc::kMidWaves, ctx->mid_lds_bytes, a, s));
+            a.hub_part = 0;
+        }
     }
     a.table_words = wg_table_words(p);
     HIP_TRY(ctx, tc::count_launch(false, a.subwave != 0, p.slots_per_bucket, pv, p.hash_kind, grid,
@@ -568,6 +596,19 @@ tc_status tc_create(int hip_device, const tc_params* p, tc_context** out) {
             return TC_E_DEVICE;
         }
         c->big_lds_bytes = (uint32_t)((c->lds_per_block_max - static_lds) & ~(size_t)15);
+        // Half-LDS launch: the largest LDS (within half a CU's, less the static part) at which the
+        // large-vertex kernel is resident twice per CU (the runtime's accounting may add a little).
+        if (prop.maxSharedMemoryPerMultiProcessor > 2 * (size_t)static_lds) {
+            uint32_t lds = (uint32_t)((prop.maxSharedMemoryPerMultiProcessor / 2 - static_lds) & ~(size_t)15);
+            for (int i = 0; i < 16 && lds > 4096; ++i, lds -= 256) {
+                int q = 0;
+                if (tc::count_kernel_info(true, false, 4, true, 0, 64 * tc::kMidWaves, lds, &q) != hipSuccess) break;
+                if (q >= 2) {
+                    c->mid_lds_bytes = lds;
+                    break;
+                }
+            }
+        }
         if (static_scratch(hip_device, &c->static_scratch) != hipSuccess) {
             delete c;
             return TC_E_DEVICE;
@@ -773,6 +814,8 @@ tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out)
     out->n_wg = m.bins[2];
     out->n_wave = m.bins[3];
     out->n_packed = m.bins[4];
+    out->n_mid = m.bins[1] - m.big_full;
+    out->mid_cap = g->caps.mid_cap;
     if (m.err & 1u) return TC_E_RANGE;
     return TC_OK;
 }

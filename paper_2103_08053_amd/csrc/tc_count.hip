@@ -873,7 +873,11 @@ __device__ __forceinline__ void add_workgroup_total(const CountArgs& a, unsigned
 // Large vertices (bins 0 and 1), launched before the main kernel with one
 // workgroup per CU and the whole LDS: bin 1 tables fill the workgroup's LDS;
 // bin 0 tables (too large for any LDS) live in global memory, one region per
-// participating workgroup (the first hub_wgs workgroups).
+// participating workgroup (the first hub_wgs workgroups).  The bin-1 vertices
+// whose tables fit half a CU's LDS go to a second launch of the same kernel
+// (hub_part 1) with half the LDS per workgroup, so two workgroups share a CU:
+// one builds or clears its table while the other probes, with twice the
+// wavefronts in flight to cover the list reads.
 template <int S, bool PV, int HK, bool MULTI>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) tc_hub_kernel(CountArgs a) {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -883,14 +887,24 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     unsigned long long acc = 0;
     AccSink sink;
-    uint32_t n_hub, n_big;
+    // Bin-1 items [lo1, hi1) taken by this launch from queue head1: the full-LDS part (all of bin 1 in
+    // multi-graph mode) with bin 0, or the half-LDS part alone.
+    uint32_t n_hub, lo1 = 0, hi1, head1 = 1, base1 = 0;
     if constexpr (MULTI) {
         n_hub = a.multi->items_tot[0];
-        n_big = a.multi->items_tot[1];
+        hi1 = a.multi->items_tot[1];
     } else {
         n_hub = a.meta->bins[0];
-        n_big = a.meta->bins[1];
+        base1 = n_hub;  // bin 1 follows bin 0 in the item order
+        hi1 = a.meta->big_full;
+        if (a.hub_part) {
+            n_hub = 0;
+            lo1 = hi1;
+            hi1 = a.meta->bins[1];
+            head1 = kMidHead;
+        }
     }
+    const uint32_t n_big = hi1 - lo1;
     if (n_hub + n_big == 0) return;
     uint32_t* const queue = lds + a.table_words + (size_t)wave * kQueueWords;
     // Item j of bin `bin` (launch-wide index in multi-graph mode) with its graph's arguments.
@@ -905,7 +919,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
             process_wg<S, PV, HK, decltype(wg)::value>(v, d.items[bin_base(d.meta, bin) + j - pre[g]], tbl, avail, tid,
                                                        wave, nw, lane, s_wsum, acc, queue, part, parts);
         } else {
-            process_wg<S, PV, HK, decltype(wg)::value>(a, a.items[(bin ? n_hub : 0u) + j], tbl, avail, tid, wave, nw,
+            process_wg<S, PV, HK, decltype(wg)::value>(a, a.items[(bin ? base1 : 0u) + j], tbl, avail, tid, wave, nw,
                                                        lane, s_wsum, acc, queue, part, parts);
         }
     };
@@ -926,12 +940,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
     if (n_big) {
         const uint32_t parts = parts_for(n_big, gridDim.x);
         for (;;) {
-            if (tid == 0) s_item = atomicAdd(&a.heads[1 * kHeadStride], 1u);
+            if (tid == 0) s_item = atomicAdd(&a.heads[head1 * kHeadStride], 1u);
             __syncthreads();
             const uint32_t t = s_item;
             __syncthreads();
             if (t >= n_big * parts) break;
-            run(1u, t / parts, lds, a.table_words, t % parts, parts, std::true_type{});
+            run(1u, lo1 + t / parts, lds, a.table_words, t % parts, parts, std::true_type{});
         }
     }
     if constexpr (MULTI) sink.to(nullptr, acc, lane);

@@ -11,12 +11,18 @@ namespace tc {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash slot; never a valid id (ids < n <= 2^32 - 1)
 constexpr uint32_t kMaxWaves = 16;
+// Wavefronts of a workgroup of the half-LDS large-vertex launch.  The kernel's scalar registers allow 7
+// wavefronts per SIMD: two 12-wavefront workgroups (3 per SIMD each) are resident together, where two
+// 16-wavefront ones are not, and capping the kernel at 8 per SIMD spills scalar registers (measured
+// slower than one workgroup per CU).
+constexpr uint32_t kMidWaves = 12;
 constexpr uint32_t kHubWgs = 128;        // workgroups that take global-memory-table vertices
-// Queue heads of the count launches: bins 0-2 and kWaveQueues sub-queues of each wavefront bin, each
-// counter in a 128-byte line of its own (kHeadStride words apart).
+// Queue heads of the count launches: bins 0-2, kWaveQueues sub-queues of each wavefront bin, then the
+// half-LDS part of bin 1, each counter in a 128-byte line of its own (kHeadStride words apart).
 constexpr uint32_t kWaveQueues = 8;
 constexpr uint32_t kHeadStride = 32;
-constexpr uint32_t kHeadWords = (3 + 2 * kWaveQueues) * kHeadStride;
+constexpr uint32_t kMidHead = 3 + 2 * kWaveQueues;
+constexpr uint32_t kHeadWords = (kMidHead + 1) * kHeadStride;
 // Packed bin: out-degree at most 32 and collective degree W(u) at most this (a few steps of 16 lanes).
 constexpr uint32_t kPackMaxWork = 512;
 constexpr uint32_t kPackMaxD = 32;
@@ -25,7 +31,7 @@ constexpr uint32_t kPackMaxD = 32;
 struct GraphMeta {
     unsigned long long m;           // oriented edges
     unsigned long long wplus;       // W+ = sum over oriented (u, v) of d+(v)
-    unsigned int reserved0;
+    unsigned int big_full;          // bin-1 vertices whose tables need more than half a CU's LDS (first in bin 1)
     unsigned int max_dplus;
     unsigned int err;               // bit 0: some input id >= n
     // vertex counts: global-memory tables, large LDS tables (one workgroup per CU), workgroup LDS
@@ -203,6 +209,7 @@ struct BuildTemp {
 
 struct BinCaps {
     uint32_t wave_cap, wg_cap, big_cap;
+    uint32_t mid_cap;   // bin-1 out-degrees counted with half a CU's LDS, two workgroups per CU (0: none)
     uint32_t pack_cap;  // out-degree limit of the packed bin (0: no packing)
     bool force_wg, force_hub, force_big, lpt, scatter_csr;
     uint32_t order;  // hash-id order: 0 (degree, id) rank, 1 in-degree, 2 collective degree
@@ -274,6 +281,8 @@ struct CountArgs {
     uint32_t* hub_scratch;           // hub_wgs * hub_words words
     unsigned long long hub_words;
     uint32_t hub_wgs;                // workgroups of the large-table launch that take global-table vertices
+    uint32_t hub_part;               // large-vertex kernel: 0 bin 0 and the full-LDS part of bin 1 (all of
+                                     // it in multi-graph mode), 1 the half-LDS part of bin 1
     uint32_t slice_words;            // per-wavefront LDS table slice (each wavefront region: the slice,
                                      // then its probe queue of kQueueWords)
     uint32_t table_words;            // LDS words of the workgroup table region (of this launch); the

@@ -337,23 +337,26 @@ __global__ void k_pack_census(const int64_t* __restrict__ off, const unsigned lo
 // (bin << 24 | reversed work, clamped to 24 bits).  Bins: 0 global-memory table (too large for
 // any LDS table), 1 large LDS table (whole LDS of a workgroup, one per CU),
 // 2 workgroup LDS table, 3 wavefront LDS slice, 4 light vertices packed
-// several to a wavefront, 5 skipped.
+// several to a wavefront, 5 skipped.  Bin 1 is split in two parts, each by decreasing work: first
+// the vertices whose tables need more than half a CU's LDS (counted by one workgroup per CU), then
+// those up to caps.mid_cap (two workgroups per CU); the work field there takes 23 bits.
 __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long long* __restrict__ wscan, uint32_t n,
                            BinCaps caps, GraphMeta* meta, uint32_t* __restrict__ skey) {
     __shared__ unsigned long long s_w;
-    __shared__ unsigned int s_max, s_bins[6];
+    __shared__ unsigned int s_max, s_bins[6], s_full;
     __shared__ unsigned long long s_bw[6];
     if (threadIdx.x < 6) {
         s_bins[threadIdx.x] = 0;
         s_bw[threadIdx.x] = 0;
     }
-    if (threadIdx.x == 0) { s_w = 0; s_max = 0; }
+    if (threadIdx.x == 0) { s_w = 0; s_max = 0; s_full = 0; }
     __syncthreads();
     const unsigned long long kWorkMax = (1ull << 24) - 1;  // larger work ties: LPT order is a heuristic
+    const unsigned long long kWorkMax1 = (1ull << 23) - 1;  // bin 1: below the part bit
     const uint32_t pack_cap = (caps.pack_cap && 2ull * meta->pack_cands >= meta->wave_cands) ? caps.pack_cap : 0u;
     // Per-thread partials, reduced across the wave, then one LDS atomic per wave.
     unsigned long long wsum = 0;
-    uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0, nb5 = 0;
+    uint32_t dmax = 0, nb0 = 0, nb1 = 0, nb2 = 0, nb3 = 0, nb4 = 0, nb5 = 0, nfull = 0;
     unsigned long long bw[6] = {0, 0, 0, 0, 0, 0};
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         const int64_t b = off[r], e = off[r + 1];
@@ -366,8 +369,15 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         else if (caps.force_wg || d > caps.wave_cap) bin = 2;
         else if (d <= pack_cap && w <= kPackMaxWork) bin = 4;
         else bin = 3;
-        const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
-        skey[r] = (bin << 24) | (uint32_t)(caps.lpt ? (kWorkMax - wk) : 0ull);
+        if (bin == 1) {
+            const uint32_t half = d <= caps.mid_cap ? 1u : 0u;
+            const unsigned long long wk = w > kWorkMax1 ? kWorkMax1 : w;
+            skey[r] = (1u << 24) | (half << 23) | (uint32_t)(caps.lpt ? (kWorkMax1 - wk) : 0ull);
+            nfull += half ^ 1u;
+        } else {
+            const unsigned long long wk = w > kWorkMax ? kWorkMax : w;
+            skey[r] = (bin << 24) | (uint32_t)(caps.lpt ? (kWorkMax - wk) : 0ull);
+        }
         wsum += w;
 #pragma unroll
         for (int q = 0; q < 6; ++q) bw[q] += (bin == (uint32_t)q) ? w : 0ull;
@@ -391,6 +401,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         nb3 += __shfl_xor(nb3, o);
         nb4 += __shfl_xor(nb4, o);
         nb5 += __shfl_xor(nb5, o);
+        nfull += __shfl_xor(nfull, o);
     }
     if ((threadIdx.x & 63) == 0) {
         atomicAdd(&s_w, wsum);
@@ -401,6 +412,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         atomicAdd(&s_bins[3], nb3);
         atomicAdd(&s_bins[4], nb4);
         atomicAdd(&s_bins[5], nb5);
+        if (nfull) atomicAdd(&s_full, nfull);
 #pragma unroll
         for (int q = 0; q < 6; ++q)
             if (bw[q]) atomicAdd(&s_bw[q], bw[q]);
@@ -409,6 +421,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
     if (threadIdx.x == 0) {
         atomicAdd(&meta->wplus, s_w);
         atomicMax(&meta->max_dplus, s_max);
+        if (s_full) atomicAdd(&meta->big_full, s_full);
         for (int i = 0; i < 6; ++i) atomicAdd(&meta->bins[i], s_bins[i]);
         for (int i = 0; i < 6; ++i)
             if (s_bw[i]) atomicAdd(&meta->bin_work[i], s_bw[i]);

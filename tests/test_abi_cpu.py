@@ -34,9 +34,20 @@ def test_static_scratch_size_matches_header():
     assert tc.TC_STATIC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
 
 
+def _header_fields(struct):
+    """(type, name) of every field of `typedef struct <struct> { ... }` in the public header."""
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (struct, struct), text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return re.findall(r"(uint32_t|uint64_t)\s+(\w+);", body)
+
+
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(tc._Params) == 10 * 4
-    assert ctypes.sizeof(tc._GraphInfo) == 3 * 8 + 10 * 4
+    for struct, cls in (("tc_params", tc._Params), ("tc_graph_info", tc._GraphInfo)):
+        fields = _header_fields(struct)
+        want = [(name, ctypes.c_uint64 if t == "uint64_t" else ctypes.c_uint32) for t, name in fields]
+        assert [(n, c) for n, c in cls._fields_] == want, struct
+        assert ctypes.sizeof(cls) == sum(8 if t == "uint64_t" else 4 for t, _ in fields)
 
 
 def test_default_params():
@@ -60,7 +71,7 @@ def test_status_strings():
 @pytest.mark.parametrize("field,value", [
     ("struct_size", 3), ("wg_waves", 0), ("wg_waves", 17), ("wg_lds_bytes", 1024),
     ("wg_lds_bytes", 4100), ("slots_per_bucket", 3), ("load_factor_pct", 5), ("load_factor_pct", 101),
-    ("hash_kind", 2), ("light_chunk", 0), ("light_chunk", 300), ("flags", 0x2000), ("flags", 0xC0), ("flags", 0x300),
+    ("hash_kind", 2), ("light_chunk", 0), ("light_chunk", 300), ("flags", 0x4000), ("flags", 0xC0), ("flags", 0x300),
 ])
 def test_create_rejects_bad_params_before_touching_a_device(field, value):
     lib = tc.load_library()

@@ -111,6 +111,7 @@ FORCED = [
     dict(flags=0x100), dict(flags=0x200), dict(flags=0x400), dict(flags=0x800),   # subwave / per-wave lists
     dict(flags=0x100 | 4), dict(flags=0x200 | 32), dict(flags=0x400 | 2, slots_per_bucket=1, load_factor_pct=100),
     dict(wg_lds_bytes=4096, wg_waves=2),        # tiny LDS: most vertices spill to the global-table bin
+    dict(wg_lds_bytes=4096, wg_waves=2, flags=0x2000),   # ... with every large-LDS vertex in the full launch
     dict(slots_per_bucket=1), dict(slots_per_bucket=4),
     dict(load_factor_pct=100), dict(load_factor_pct=10),
     dict(slots_per_bucket=1, load_factor_pct=100, flags=2),   # long probe chains in LDS
@@ -150,7 +151,33 @@ def test_bins_are_exercised(torch):
     c = Context(0, Params(wg_lds_bytes=4096, wg_waves=2))
     small = c.build(g.src, g.dst, g.n).info()
     assert small.n_big > 0 and small.n_hub == 0
+    assert 0 < small.n_mid <= small.n_big and small.wg_cap < small.mid_cap < small.big_cap
     assert_parity(c, g)
+
+
+def test_half_lds_launch(torch):
+    """Large-LDS-bin vertices in both launches: K_2500 has out-degrees 0..2499 in rank order, so
+    those above the half-LDS limit (about 2000) take the full-LDS launch and those between the
+    workgroup limit and it the half-LDS one; every count is the closed form, with and without the
+    split, and the split changes no count."""
+    from paper_2103_08053_amd import Context, Params
+    n = 2500
+    g = gg.complete(n)
+    res = {}
+    for flags in (0, 0x2000):
+        c = Context(0, Params(flags=flags))
+        graph = c.build(g.src, g.dst, g.n)
+        info = graph.info()
+        say(f"[gpu] K_{n} flags={flags:#x} n_big={info.n_big} n_mid={info.n_mid} mid_cap={info.mid_cap}")
+        tot, pv = graph.count(per_vertex=True)
+        pv = pv.cpu().numpy().astype(np.uint64)
+        assert tot == comb(n, 3)
+        assert (pv == comb(n - 1, 2)).all()
+        res[flags] = info
+    on, off = res[0], res[0x2000]
+    assert on.wg_cap < on.mid_cap < on.big_cap and off.mid_cap == 0 and off.n_mid == 0
+    assert on.n_big == off.n_big and 0 < on.n_mid < on.n_big
+    assert on.n_big - on.n_mid == sum(1 for d in range(n) if d > on.mid_cap)
 
 
 # ----------------------------------------------------------------------------- edge cases

@@ -92,6 +92,13 @@ typedef struct tc_params {
 #define TC_F_NO_MID      0x2000u /* every large-LDS-bin vertex in the full-LDS launch (one workgroup per
                                     CU); default: those whose tables fit half a CU's LDS are counted by a
                                     second launch with two workgroups per CU */
+#define TC_F_RECORDS     0x4000u /* the build also lays each vertex's out-degree and out-list out as one
+                                    record (d+, then the neighbours' record positions), and single-graph
+                                    counts read lists through it: a 2-hop list starts in the line of its
+                                    length instead of behind a separate offset load.  Not with the
+                                    TC_F_ORDER_* relabellings or TC_F_SCATTER_CSR (ignored there); the
+                                    graph's storage grows by 4 (m_in + n + 1) bytes and a per-vertex
+                                    count's scratch by 8 (m_in + 1) bytes */
 
 /* Opaque handles. */
 typedef struct tc_context tc_context;
@@ -115,7 +122,7 @@ typedef struct tc_graph_info {
     uint32_t n_mid;       /* vertices of the large-LDS bin (counted in n_big) whose tables fit half a CU's
                              LDS: a second launch counts them with two workgroups per CU */
     uint32_t mid_cap;     /* out-degree limit of that part (0: no such launch) */
-    uint32_t reserved;
+    uint32_t records;     /* 1: built with the record layout (TC_F_RECORDS), which single-graph counts read */
 } tc_graph_info;
 
 /* Fill *p with the default knobs (struct_size set). */

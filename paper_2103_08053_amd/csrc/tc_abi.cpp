@@ -150,7 +150,7 @@ tc_status check_params(const tc_params* p) {
     if (p->light_chunk < 1 || p->light_chunk > 256) return TC_E_INVALID;
     if (p->flags & ~(TC_F_NO_LPT | TC_F_FORCE_WG | TC_F_FORCE_HUB | TC_F_SCATTER_CSR | TC_F_WIDE_ADDR |
                      TC_F_FORCE_BIG | TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE | kIntraFlags | TC_F_NO_PACK |
-                     TC_F_NO_MID))
+                     TC_F_NO_MID | TC_F_RECORDS))
         return TC_E_INVALID;
     if (__builtin_popcount(p->flags & kIntraFlags) > 1) return TC_E_INVALID;
     if ((p->flags & TC_F_ORDER_INDEGREE) && (p->flags & TC_F_ORDER_COLLECTIVE)) return TC_E_INVALID;
@@ -221,8 +221,17 @@ uint32_t dplus_bound(uint32_t n, uint64_t m_in) {
     return (uint32_t)b;
 }
 
+// Whether a graph of n vertices and m_in samples built with p gets the record layout: asked for, a
+// build that sorts the oriented edges in rank order, and record positions and list starts below 2^31.
+bool records_on(const tc_params& p, uint32_t n, uint64_t m_in) {
+    return (p.flags & TC_F_RECORDS) &&
+           !(p.flags & (TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE | TC_F_SCATTER_CSR)) &&
+           m_in + n + 1 < (1ull << 31);
+}
+
 Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_in, bool batch = false) {
     Layout L{};
+    L.records = records_on(p, n, m_in);
     size_t o = 0;
     L.s_meta = o;  o = align_up(o + sizeof(tc::GraphMeta));
     L.s_off = o;   o = align_up(o + sizeof(int64_t) * ((size_t)n + 1));
@@ -231,6 +240,7 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     L.s_rank = o;  o = align_up(o + sizeof(uint32_t) * (size_t)n);
     L.s_items = o; o = align_up(o + sizeof(uint32_t) * (size_t)n);
     L.s_gid = o;   o = align_up(o + (batch ? sizeof(uint32_t) * (size_t)n : 0));
+    L.s_rec = o;   o = align_up(o + (L.records ? sizeof(uint32_t) * ((size_t)m_in + n + 1) : 0));
     L.storage = o;
 
     o = 0;
@@ -256,7 +266,8 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     // separately allocated scratch begins) the per-vertex count at R-MAT scale 22 measured 18.8 ms
     // against 17.3-17.9 ms anywhere past its first 8 KB, so they go last.
     o = 0;
-    L.c_tv = o;     o = align_up(o + 8 * (size_t)n);
+    // (record layout: the per-vertex counts are kept by record position)
+    L.c_tv = o;     o = align_up(o + 8 * (L.records ? (size_t)m_in + n + 1 : (size_t)n));
     const uint32_t dmax = dplus_bound(n, m_in);
     L.hub_words = tc::geometry(dmax, p.slots_per_bucket, tc::load_recip(p.load_factor_pct), true).words;
     uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)std::max(1, ctx ? ctx->cu_count : 1);
@@ -278,6 +289,7 @@ tc::GraphDev graph_ptrs(void* storage, const Layout& L) {
     g.rank = reinterpret_cast<uint32_t*>(b + L.s_rank);
     g.items = reinterpret_cast<uint32_t*>(b + L.s_items);
     g.gid = nullptr;
+    g.rec = L.records ? reinterpret_cast<uint32_t*>(b + L.s_rec) : nullptr;
     return g;
 }
 
@@ -321,6 +333,7 @@ tc_status build_into(tc_context* ctx, tc_graph* g, uint32_t n, uint64_t m_in, co
     g->k = batch ? batch->k : 1;
     g->p = ctx->p;
     g->caps = bin_caps(ctx, ctx->p);
+    g->caps.records = L.records;
     g->empty = (n == 0 || m_in == 0);
     if (g->empty) {
         g->dev = tc::GraphDev{};
@@ -407,6 +420,13 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.lrecip = tc::load_recip(p.load_factor_pct);
     a.chunk = p.light_chunk;
     a.wide = tc::wide_list_addressing(g->m_in, (p.flags & TC_F_WIDE_ADDR) != 0) ? 1u : 0u;
+    // Record layout: lists are read through the records, and ids (tables, tallies) are record positions.
+    const size_t tv_words = g->dev.rec ? (size_t)g->m_in + g->n + 1 : (size_t)g->n;
+    if (g->dev.rec) {
+        a.rec = g->dev.rec;
+        a.col = g->dev.rec;
+        a.wide = tc::wide_list_addressing(g->m_in + g->n + 1, (p.flags & TC_F_WIDE_ADDR) != 0) ? 1u : 0u;
+    }
     a.shard = shard;
     a.shards = shards;
     a.subwave = subwave_lanes(p.flags);
@@ -425,7 +445,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     if (grid_hub < a.hub_wgs) a.hub_wgs = grid_hub;
     HIP_TRY(ctx, tc::fill_u32(a.heads, 0, tc::kHeadWords, s));
     HIP_TRY(ctx, tc::fill_u32(d_totals, 0, 2 * (size_t)g->k, s));
-    if (pv) HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * (size_t)g->n, s));
+    if (pv) HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * tv_words, s));
     const bool rec = record && ctx->timing;
     if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
     if (hub) {
@@ -449,7 +469,9 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
         HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
         ctx->have_count = true;
     }
-    if (pv) HIP_TRY(ctx, tc::gather_per_vertex(a.tv, g->dev.rank, g->n, reinterpret_cast<unsigned long long*>(d_per_vertex), s));
+    if (pv)
+        HIP_TRY(ctx, tc::gather_per_vertex(a.tv, g->dev.rank, g->n, g->dev.rec ? g->dev.off32 : nullptr,
+                                           reinterpret_cast<unsigned long long*>(d_per_vertex), s));
     return TC_OK;
 }
 
@@ -800,6 +822,7 @@ tc_status tc_graph_info_get(const tc_graph* g, void* stream, tc_graph_info* out)
     out->wave_cap = g->caps.wave_cap;
     out->wg_cap = g->caps.wg_cap;
     out->big_cap = g->caps.big_cap;
+    out->records = g->dev.rec ? 1u : 0u;
     if (g->empty) return TC_OK;
     tc::GraphMeta m;
     if (hipSetDevice(g->ctx->device) != hipSuccess) return TC_E_DEVICE;

@@ -528,6 +528,26 @@ struct NoMid {
     __device__ void operator()() const {}
 };
 
+// 2-hop list of vertex w: col[start, start + len).  Record layout: w is a record position, the length
+// heads the record and the list follows it (one line for both in the common case); otherwise w is a
+// rank and the bounds come from the offsets (a line of their own).
+__device__ __forceinline__ void list_of(const CountArgs& a, uint32_t w, uint32_t& start, uint32_t& len) {
+    if (a.rec) {
+        len = a.rec[w];
+        start = w + 1u;
+    } else {
+        start = a.off[w];
+        len = a.off[w + 1] - start;
+    }
+}
+
+// Table owner u (a rank) as the lists name it (its record position, or u), and where its own list
+// starts in col.
+__device__ __forceinline__ uint32_t own_id(const CountArgs& a, uint32_t u) { return a.rec ? a.off[u] + u : u; }
+__device__ __forceinline__ uint32_t own_start(const CountArgs& a, uint32_t u) {
+    return a.rec ? a.off[u] + u + 1u : a.off[u];
+}
+
 // u's list is col[beg, beg + d) (uniform values).  With `pre` (one wavefront, d <= 64; uniform) the
 // lane's list element and that element's list (start, length) were loaded by the caller (xw, xo, xl).
 // `mid` runs after the table is built and before the probe (the caller issues its next loads there).
@@ -583,8 +603,9 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
         for (uint32_t p = gl; p < d; p += gsz) {
             const uint32_t w = a.col[beg + p];
             insert(w);
-            const int64_t o0 = a.off[w], o1 = a.off[w + 1];
-            P[p] = u32x2{(uint32_t)(o1 - o0), (uint32_t)o0};
+            uint32_t st, ln;
+            list_of(a, w, st, ln);
+            P[p] = u32x2{ln, st};
         }
     }
     group_sync<WG>();
@@ -640,7 +661,7 @@ __device__ __forceinline__ void process(const CountArgs& a, uint32_t u, int64_t 
     }
 
     if constexpr (PV) {
-        if (lane == 0 && hits) atomicAdd(&a.tv[u], hits);
+        if (lane == 0 && hits) atomicAdd(&a.tv[own_id(a, u)], hits);
         group_sync<WG>();
         for (uint32_t p = gl; p < d; p += gsz) {
             const uint32_t t = tally[p];
@@ -702,8 +723,7 @@ __device__ __forceinline__ void process_packed(const CountArgs& a, uint32_t ug, 
             b = (b + 1) & geo.mask;
         }
         slots[b * S + pos] = w;
-        o0 = (uint32_t)a.off[w];
-        lv = (uint32_t)a.off[w + 1] - o0;
+        list_of(a, w, o0, lv);
     }
     const uint32_t incl = group_incl_scan<G>(lv);
     const uint32_t W = (uint32_t)__shfl((int)incl, (int)(g * G + G - 1), 64);
@@ -768,7 +788,7 @@ __device__ __forceinline__ void process_packed(const CountArgs& a, uint32_t ug, 
         acc += sum;
     }
     if constexpr (PV) {
-        if (last && has && hs) atomicAdd(&a.tv[ug], (unsigned long long)hs);
+        if (last && has && hs) atomicAdd(&a.tv[own_id(a, ug)], (unsigned long long)hs);
         wave_sync();
         if (gl < d) {
             const uint32_t t = tally[gl];
@@ -846,8 +866,8 @@ __device__ __forceinline__ void process_wg(const CountArgs& a, uint32_t u, uint3
                                            uint32_t* queue, uint32_t part = 0, uint32_t parts = 1) {
     u = __builtin_amdgcn_readfirstlane(u);
     if (!in_shard(a, u)) return;
-    const int64_t beg = a.off[u];
-    const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(a.off[u + 1] - beg));
+    const int64_t beg = own_start(a, u);
+    const uint32_t d = __builtin_amdgcn_readfirstlane(a.off[u + 1] - a.off[u]);
     process<S, PV, HK, true, DEFER, NoMid, SW>(a, u, beg, d, tbl, avail, tid, blockDim.x, wave, nw, lane, s_wsum, acc,
                                                queue, false, 0u, 0u, 0u, NoMid{}, part, parts);
 }
@@ -1056,11 +1076,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
         // (lane i holds the i-th), so each vertex starts without two dependent loads.
         for (uint32_t b0 = j0; b0 < j1; b0 += 64) {
             const uint32_t cnt = (j1 - b0 < 64u) ? j1 - b0 : 64u;
-            uint32_t vu = 0, vb = 0, vd = 0;  // offsets stay below 2^31 (m < 2^31)
+            uint32_t vu = 0, vb = 0, vd = 0;  // list starts stay below 2^31 (m < 2^31; records: m + n < 2^31)
             if ((uint32_t)lane < cnt) {
                 vu = v.items[base + b0 + lane];
-                vb = (uint32_t)v.off[vu];
-                vd = (uint32_t)v.off[vu + 1] - vb;
+                vb = own_start(v, vu);
+                vd = v.off[vu + 1] - v.off[vu];
             }
             // Two-stage prefetch for lists of at most 64: the next vertex's list is loaded while
             // this one's table is built, and its elements' list bounds while this one is probed.
@@ -1071,8 +1091,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 xw = xo = xl = 0;
                 if (d0 <= 64u && (uint32_t)lane < d0) {
                     xw = v.col[beg0 + lane];
-                    xo = (uint32_t)v.off[xw];
-                    xl = (uint32_t)v.off[xw + 1] - xo;
+                    list_of(v, xw, xo, xl);
                 }
             };
             prime(0);
@@ -1087,10 +1106,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 uint32_t nw = 0, no = 0, nl = 0;
                 if (pre_n) nw = v.col[beg_n + lane];
                 auto mid = [&]() {
-                    if (pre_n) {
-                        no = (uint32_t)v.off[nw];
-                        nl = (uint32_t)v.off[nw + 1] - no;
-                    }
+                    if (pre_n) list_of(v, nw, no, nl);
                 };
                 if (in_shard(v, u))
                     process<S, PV, HK, false, true, decltype(mid), SW>(v, u, beg, d, slice, a.slice_words, lane,
@@ -1115,8 +1131,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) 
                 uint32_t vu = 0, vb = 0, vd = 0;
                 if ((uint32_t)lane < cnt) {
                     vu = v.items[base + b0 + lane];
-                    vb = (uint32_t)v.off[vu];
-                    vd = (uint32_t)v.off[vu + 1] - vb;
+                    vb = own_start(v, vu);
+                    vd = v.off[vu + 1] - v.off[vu];
                 }
                 for (uint32_t i = 0; i < cnt;) {
                     uint32_t n16 = 0;

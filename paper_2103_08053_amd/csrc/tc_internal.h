@@ -181,6 +181,8 @@ struct GraphDev {
     uint32_t* rank;     // [n] input id -> rank
     uint32_t* items;    // [n] scheduled vertices by bin (global table, large LDS, workgroup, wavefront, packed, skipped)
     uint32_t* gid;      // [n] graph index of each rank (batches only, else null)
+    uint32_t* rec;      // [m_in + n + 1] vertex records (record layout only, else null): rank r's record
+                        // at p(r) = off[r] + r holds d+(r), then p(v) of each out-neighbour v
 };
 
 // Batch description for the build (device arrays of k + 1 offsets).
@@ -212,17 +214,19 @@ struct BinCaps {
     uint32_t mid_cap;   // bin-1 out-degrees counted with half a CU's LDS, two workgroups per CU (0: none)
     uint32_t pack_cap;  // out-degree limit of the packed bin (0: no packing)
     bool force_wg, force_hub, force_big, lpt, scatter_csr;
+    bool records;       // build the record layout (GraphDev::rec)
     uint32_t order;  // hash-id order: 0 (degree, id) rank, 1 in-degree, 2 collective degree
 };
 
 struct Layout {
     size_t storage, temp, scratch;
     // storage offsets
-    size_t s_meta, s_off, s_off32, s_col, s_rank, s_items, s_gid;
+    size_t s_meta, s_off, s_off32, s_col, s_rank, s_items, s_gid, s_rec;
     // temp offsets
     size_t t_keys_a, t_keys_b, t_aux, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_rk_a, t_rk_b, t_off2, t_sort;
     size_t sort_tmp_bytes;
     bool relabel;  // temp holds the relabelling arrays
+    bool records;  // storage holds the record layout, per-vertex scratch is indexed by record position
     // scratch offsets
     size_t c_tv, c_heads, c_total, c_hub;
     uint64_t hub_words;
@@ -293,6 +297,8 @@ struct CountArgs {
     uint32_t subwave;                // 0: virtual combination; 8/16/32/64: lanes per out-neighbour list
     uint32_t shard, shards;          // count only table owners u (rank) with u % shards == shard
     uint32_t wide;                   // col spans 4 GiB or more: 64-bit addressing in the probe
+    const uint32_t* rec;             // record layout (col == rec): ids are record positions, tv is indexed
+                                     // by them, and vertex w's list is rec[w + 1, w + 1 + rec[w])
 };
 
 // tc_prep.hip
@@ -301,7 +307,8 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
                       const GraphDev& g, const BuildTemp& t, const BinCaps& caps, const BatchIn* batch,
                       hipStream_t stream);
 hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream);
-hipError_t gather_per_vertex(const unsigned long long* tv_rank, const uint32_t* rank, uint32_t n,
+// out[x] = tv[id(rank[x])] with id(r) = r, or the record position off32[r] + r when off32 is given.
+hipError_t gather_per_vertex(const unsigned long long* tv, const uint32_t* rank, uint32_t n, const uint32_t* off32,
                              unsigned long long* out, hipStream_t stream);
 
 // tc_diag.hip: per-table collision statistics of a built graph (the cost model of Equation 2) for

@@ -15,6 +15,8 @@
 //     (the reordering idea of Section 4.1; other orders are optional);
 //  5. CSR: stable radix sort of the oriented keys by row, row lengths from key
 //     runs, scan (int64 offsets);
+//  5c (optional): the record layout: rank r's record at p(r) = off[r] + r holds d+(r) and then
+//     p(v) for each out-neighbour v (written during the scan of step 6, which gathers d+(v) anyway);
 //  6. scheduling (Section 4.3): out-degree d+ and collective work
 //     W(u) = sum of d+(v) over out-neighbours v (the collective degree of
 //     Equation 2); vertices with d+ < 2 or W = 0 are skipped, the rest go by
@@ -111,6 +113,25 @@ struct HeadOutDegree {
     const GraphMeta* meta;
     __device__ unsigned long long operator()(uint64_t e) const {
         return e < meta->m ? (unsigned long long)dplus[col[e]] : 0ull;
+    }
+};
+
+// Record layout: d+(v) and p(v) = off[v] + v of rank v packed in one word (d+ high), gathered once per
+// edge.  For edge e (row r, head v: the sorted oriented key r << nb | v) the scan of d+(v) writes
+// p(v) into r's record as a side effect (element e + r + 1 of rec; idempotent if evaluated twice).
+struct RecordHead {
+    const unsigned long long* okeys;
+    const unsigned long long* packed;
+    uint32_t* rec;
+    uint32_t nb;
+    unsigned long long mask;
+    const GraphMeta* meta;
+    __device__ unsigned long long operator()(uint64_t e) const {
+        if (e >= meta->m) return 0ull;
+        const unsigned long long k = okeys[e];
+        const unsigned long long pk = packed[k & mask];
+        rec[e + (k >> nb) + 1] = (uint32_t)pk;
+        return pk >> 32;
     }
 };
 
@@ -341,7 +362,7 @@ __global__ void k_pack_census(const int64_t* __restrict__ off, const unsigned lo
 // the vertices whose tables need more than half a CU's LDS (counted by one workgroup per CU), then
 // those up to caps.mid_cap (two workgroups per CU); the work field there takes 23 bits.
 __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long long* __restrict__ wscan, uint32_t n,
-                           BinCaps caps, GraphMeta* meta, uint32_t* __restrict__ skey) {
+                           BinCaps caps, GraphMeta* meta, uint32_t* __restrict__ skey, uint32_t* __restrict__ rec) {
     __shared__ unsigned long long s_w;
     __shared__ unsigned int s_max, s_bins[6], s_full;
     __shared__ unsigned long long s_bw[6];
@@ -362,6 +383,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         const int64_t b = off[r], e = off[r + 1];
         const uint32_t d = (uint32_t)(e - b);
         const unsigned long long w = d ? wscan[e - 1] - (b ? wscan[b - 1] : 0ull) : 0ull;
+        if (rec) rec[b + r] = d;  // the record's header
         uint32_t bin;
         if (d < 2 || w == 0) bin = 5;
         else if (caps.force_hub || d > caps.big_cap) bin = 0;
@@ -504,9 +526,19 @@ __global__ void k_scatter_u32(const uint32_t* __restrict__ in, const uint32_t* _
 }
 
 __global__ void k_gather(const unsigned long long* __restrict__ tv, const uint32_t* __restrict__ rank, uint32_t n,
-                         unsigned long long* __restrict__ out) {
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x)
-        out[x] = tv[rank[x]];
+                         const uint32_t* __restrict__ off32, unsigned long long* __restrict__ out) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+        const uint32_t r = rank[x];
+        out[x] = tv[off32 ? (uint64_t)off32[r] + r : (uint64_t)r];
+    }
+}
+
+// Record layout: d+(r) << 32 | p(r) for every rank.
+__global__ void k_pack_records(const int64_t* __restrict__ off, uint32_t n, unsigned long long* __restrict__ packed) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int64_t b = off[r];
+        packed[r] = ((unsigned long long)(off[r + 1] - b) << 32) | (unsigned long long)(b + r);
+    }
 }
 
 #define TC_TRY(expr)                        \
@@ -523,10 +555,10 @@ hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t gather_per_vertex(const unsigned long long* tv_rank, const uint32_t* rank, uint32_t n,
+hipError_t gather_per_vertex(const unsigned long long* tv, const uint32_t* rank, uint32_t n, const uint32_t* off32,
                              unsigned long long* out, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, stream, tv_rank, rank, n, out);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, stream, tv, rank, n, off32, out);
     return hipGetLastError();
 }
 
@@ -554,6 +586,11 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
         auto heads = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
                                                       HeadOutDegree{u32p, u32p, nullptr});
         if (rocprim::inclusive_scan(nullptr, sz, heads, k64, (size_t)m_in, rocprim::plus<unsigned long long>()) ==
+                hipSuccess && sz > best) best = sz;
+        sz = 0;
+        auto rheads = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
+                                                       RecordHead{k64, k64, u32p, 1u, 1ull, nullptr});
+        if (rocprim::inclusive_scan(nullptr, sz, rheads, k64, (size_t)m_in, rocprim::plus<unsigned long long>()) ==
                 hipSuccess && sz > best) best = sz;
         sz = 0;
     }
@@ -733,7 +770,21 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
 
     // 6: bins and largest-work-first order; W(u) from a scan of d+(col[e]).
     unsigned long long* wscan = reinterpret_cast<unsigned long long*>(t.keys_a);
-    {
+    // 5c with it: the scan's gather of d+(v) also fetches p(v), which goes into the records (the
+    // sorted oriented keys give each edge's row; no relabelling or counting-sort build here).
+    uint32_t* rec = (caps.records && !caps.order && !caps.scatter_csr) ? g.rec : nullptr;
+    if (rec) {
+        unsigned long long* packed = reinterpret_cast<unsigned long long*>(t.skey_b);
+        hipLaunchKernelGGL(k_pack_records, dim3(grid_for(n)), dim3(kThreads), 0, stream, g.off, n, packed);
+        TC_TRY(hipGetLastError());
+        const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
+        auto heads = rocprim::make_transform_iterator(
+            rocprim::make_counting_iterator<uint64_t>(0),
+            RecordHead{reinterpret_cast<const unsigned long long*>(t.aux), packed, rec, nb, mask, g.meta});
+        tmp = t.sort_tmp_bytes;
+        TC_TRY(rocprim::inclusive_scan(t.sort_tmp, tmp, heads, wscan, (size_t)m_in,
+                                       rocprim::plus<unsigned long long>(), stream));
+    } else {
         auto heads = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
                                                       HeadOutDegree{g.col, t.dplus, g.meta});
         tmp = t.sort_tmp_bytes;
@@ -748,7 +799,7 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     // at most 1024 blocks: each block ends with a few global atomics on the same summary words
     uint32_t* skey = reinterpret_cast<uint32_t*>(t.skey_a);
     hipLaunchKernelGGL(k_schedule, dim3(std::min(grid_for(n), 1024u)), dim3(kThreads), 0, stream, g.off, wscan, n, caps, g.meta,
-                       skey);
+                       skey, rec);
     TC_TRY(hipGetLastError());
     tmp = t.sort_tmp_bytes;
     TC_TRY(sort_pairs(t.sort_tmp, tmp, skey, reinterpret_cast<uint32_t*>(t.skey_b), g.items, (size_t)n, kScheduleBits,

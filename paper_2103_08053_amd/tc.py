@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(PKG, "libtrust_tc.so")
 
 TC_OK, TC_E_INVALID, TC_E_RANGE, TC_E_NOMEM, TC_E_DEVICE, TC_E_UNSUPPORTED, TC_E_BUSY = range(7)
 TC_F_NO_LPT, TC_F_FORCE_WG, TC_F_FORCE_HUB, TC_F_SCATTER_CSR, TC_F_WIDE_ADDR = 0x1, 0x2, 0x4, 0x8, 0x10
-TC_F_FORCE_BIG, TC_F_NO_PACK, TC_F_NO_MID = 0x20, 0x1000, 0x2000
+TC_F_FORCE_BIG, TC_F_NO_PACK, TC_F_NO_MID, TC_F_RECORDS = 0x20, 0x1000, 0x2000, 0x4000
 
 EXPORTS = [
     "tc_default_params", "tc_create", "tc_destroy", "tc_set_params", "tc_get_params", "tc_status_str",
@@ -56,7 +56,7 @@ class _GraphInfo(ctypes.Structure):
                 ("max_dplus", ctypes.c_uint32), ("n_hub", ctypes.c_uint32), ("n_wg", ctypes.c_uint32),
                 ("n_wave", ctypes.c_uint32), ("wave_cap", ctypes.c_uint32), ("wg_cap", ctypes.c_uint32),
                 ("n_big", ctypes.c_uint32), ("big_cap", ctypes.c_uint32), ("n_packed", ctypes.c_uint32),
-                ("n_mid", ctypes.c_uint32), ("mid_cap", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("n_mid", ctypes.c_uint32), ("mid_cap", ctypes.c_uint32), ("records", ctypes.c_uint32)]
 
 
 @dataclass
@@ -100,7 +100,7 @@ class GraphInfo:
     n_packed: int = 0
     n_mid: int = 0      # large-LDS-bin vertices counted by the half-LDS launch (included in n_big)
     mid_cap: int = 0
-    reserved: int = 0
+    records: int = 0    # 1: the graph carries the record layout (TC_F_RECORDS)
 
 
 _lib = None

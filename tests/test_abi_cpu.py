@@ -71,7 +71,7 @@ def test_status_strings():
 @pytest.mark.parametrize("field,value", [
     ("struct_size", 3), ("wg_waves", 0), ("wg_waves", 17), ("wg_lds_bytes", 1024),
     ("wg_lds_bytes", 4100), ("slots_per_bucket", 3), ("load_factor_pct", 5), ("load_factor_pct", 101),
-    ("hash_kind", 2), ("light_chunk", 0), ("light_chunk", 300), ("flags", 0x4000), ("flags", 0xC0), ("flags", 0x300),
+    ("hash_kind", 2), ("light_chunk", 0), ("light_chunk", 300), ("flags", 0x8000), ("flags", 0xC0), ("flags", 0x300),
 ])
 def test_create_rejects_bad_params_before_touching_a_device(field, value):
     lib = tc.load_library()

@@ -65,9 +65,10 @@ def test_single_graph_batch(ctx):
 
 @pytest.mark.parametrize("kw", [dict(flags=2), dict(flags=4), dict(flags=32), dict(wg_lds_bytes=4096, wg_waves=2),
                                 dict(slots_per_bucket=1, load_factor_pct=100), dict(hash_kind=1),
-                                dict(flags=0x40), dict(flags=0x80), dict(flags=0x200)],
+                                dict(flags=0x40), dict(flags=0x80), dict(flags=0x200), dict(flags=0x4000),
+                                dict(flags=0x4000 | 4)],
                          ids=["wg", "hub", "big", "tinylds", "s1full", "hash1", "order_in", "order_collective",
-                              "subwave16"])
+                              "subwave16", "records", "records_hub"])
 def test_batch_forced_paths(kw):
     from paper_2103_08053_amd import Context, Params
     check_batch(Context(0, Params(**kw)), mixed_graphs()[:14])

@@ -106,9 +106,9 @@ def test_count_graphs_with_batch_handles(ctx):
 @pytest.mark.parametrize("kw", [dict(flags=2), dict(flags=4), dict(flags=32), dict(wg_lds_bytes=4096, wg_waves=2),
                                 dict(slots_per_bucket=1, load_factor_pct=100), dict(hash_kind=1),
                                 dict(flags=0x40), dict(flags=0x1000), dict(light_chunk=1), dict(grid_wgs=3),
-                                dict(flags=0x10)],
+                                dict(flags=0x10), dict(flags=0x4000)],
                          ids=["wg", "hub", "big", "tinylds", "s1full", "hash1", "order_in", "nopack", "chunk1",
-                              "grid3", "wide"])
+                              "grid3", "wide", "records"])
 def test_count_graphs_forced_paths(kw):
     from paper_2103_08053_amd import Context, Params
     c = Context(0, Params(**kw))

@@ -120,6 +120,11 @@ FORCED = [
     dict(wg_waves=1), dict(wg_waves=4), dict(wg_waves=16, wg_lds_bytes=131072),
     dict(grid_wgs=3), dict(grid_wgs=1, flags=4), dict(grid_wgs=2, flags=32), dict(wave_max_dplus=8),
     dict(flags=16), dict(flags=16 | 2, slots_per_bucket=1, load_factor_pct=100),   # 64-bit list addressing
+    # the record layout, through every bin and probe variant
+    dict(flags=0x4000), dict(flags=0x4000 | 2), dict(flags=0x4000 | 4), dict(flags=0x4000 | 32),
+    dict(flags=0x4000, wg_lds_bytes=4096, wg_waves=2), dict(flags=0x4000 | 0x1000), dict(flags=0x4000 | 0x100),
+    dict(flags=0x4000 | 0x800), dict(flags=0x4000 | 16), dict(flags=0x4000, hash_kind=1),
+    dict(flags=0x4000 | 1, slots_per_bucket=1, load_factor_pct=100), dict(flags=0x4000 | 0x40),
 ]
 
 
@@ -153,6 +158,21 @@ def test_bins_are_exercised(torch):
     assert small.n_big > 0 and small.n_hub == 0
     assert 0 < small.n_mid <= small.n_big and small.wg_cap < small.mid_cap < small.big_cap
     assert_parity(c, g)
+
+
+def test_record_layout_flag(torch):
+    """TC_F_RECORDS gives the graph its records unless a relabelling or the counting-sort build is asked
+    for; the counts agree either way (the element-wise oracle checks are the forced-path cases)."""
+    from paper_2103_08053_amd import Context, Params
+    g = gg.dirty(gg.rmat(12, 16, seed=8), seed=2)
+    res = {}
+    for flags, want in ((0, 0), (0x4000, 1), (0x4000 | 0x40, 0), (0x4000 | 0x8, 0)):
+        graph = Context(0, Params(flags=flags)).build(g.src, g.dst, g.n)
+        assert graph.info().records == want, flags
+        tot, pv = graph.count(per_vertex=True)
+        res[flags] = (tot, pv.cpu().numpy())
+    for flags in res:
+        assert res[flags][0] == res[0][0] and (res[flags][1] == res[0][1]).all(), flags
 
 
 def test_half_lds_launch(torch):

@@ -3,11 +3,13 @@
 //  1. canonicalise: each sample (a, b) becomes the key (min << nb) | max;
 //     self-loops and out-of-range ids become a sentinel that sorts last
 //     (cleaning rules of the paper, Section 2.6: duplicates and self-loops
-//     removed, directed pairs read as undirected);
-//  2. radix sort; distinct edges numbered by a scan of first-of-run flags
+//     removed, directed pairs read as undirected); single graphs form the
+//     keys as the sort reads its input;
+//  2. radix sort; distinct edges are the first keys of runs of equal keys
 //     (duplicates stay in place and are skipped downstream);
-//  3. degree of every vertex (from runs of the sorted lower and upper
-//     endpoints), then its rank in (degree, id) order;
+//  3. degree of every vertex (distinct edges per run of equal lower ids, in
+//     the pass that flags the runs; runs of the sorted upper endpoints), then
+//     its rank in (degree, id) order;
 //  4. orientation by rank-by-degree (Section 2.2): the edge runs from the
 //     lower-ranked to the higher-ranked endpoint, and every id is replaced by
 //     its rank, so out-neighbour lists hold ranks and hashing the low bits of
@@ -63,8 +65,9 @@ using Onesweep9x32 = rocprim::radix_sort_config<
     rocprim::radix_sort_onesweep_config<rocprim::kernel_config<1024, 16>, rocprim::kernel_config<1024, 16>, 9,
                                         rocprim::block_radix_rank_algorithm::match>>;
 
-hipError_t sort_keys(void* tmp, size_t& bytes, unsigned long long* in, unsigned long long* out, size_t count,
-                     uint32_t lo, uint32_t hi, hipStream_t stream) {
+template <typename In>
+hipError_t sort_keys(void* tmp, size_t& bytes, In in, unsigned long long* out, size_t count, uint32_t lo, uint32_t hi,
+                     hipStream_t stream) {
     return rocprim::radix_sort_keys<Onesweep9x64>(tmp, bytes, in, out, count, lo, hi, stream);
 }
 
@@ -95,14 +98,23 @@ uint32_t degree_bits(uint32_t n, uint64_t m_in) {
 
 constexpr uint32_t kScheduleBits = 27;  // schedule keys: bin (0-5) << 24 | 24-bit reversed work
 
-// 1 for the first key of each run of equal keys (and not the sentinel): the
-// inclusive scan of these flags numbers the distinct edges.
-struct FirstOfRun {
-    const unsigned long long* keys;
+// Canonical key of sample i, formed as the sort reads it (the key histogram and the first pass each
+// read the sample once); an out-of-range id raises the range error and gives the sentinel.
+struct CanonKey {
+    const uint32_t* src;
+    const uint32_t* dst;
+    uint32_t n, nb;
     unsigned long long sentinel;
-    __device__ uint32_t operator()(uint64_t i) const {
-        const unsigned long long k = keys[i];
-        return (k != sentinel && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+    GraphMeta* meta;
+    __device__ unsigned long long operator()(uint64_t i) const {
+        const uint32_t a = src[i], b = dst[i];
+        if (a >= n || b >= n) {
+            if (!meta->err) atomicOr(&meta->err, 1u);
+            return sentinel;
+        }
+        if (a == b) return sentinel;
+        const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+        return ((unsigned long long)lo << nb) | hi;
     }
 };
 
@@ -150,24 +162,6 @@ __global__ void k_narrow(const int64_t* __restrict__ off, uint64_t n1, uint32_t*
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t words) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
-}
-
-__global__ void k_canon(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst, uint64_t m_in,
-                        uint32_t n, uint32_t nb, unsigned long long sentinel,
-                        unsigned long long* __restrict__ keys, GraphMeta* meta) {
-    uint32_t bad = 0;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < m_in; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t a = src[i], b = dst[i];
-        unsigned long long k;
-        if (a >= n || b >= n) { bad = 1; k = sentinel; }
-        else if (a == b) k = sentinel;
-        else {
-            const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-            k = ((unsigned long long)lo << nb) | hi;
-        }
-        keys[i] = k;
-    }
-    if (bad) atomicOr(&meta->err, 1u);
 }
 
 // Largest g in [0, k) with off[g] <= x (off is non-decreasing, off[0] = 0).
@@ -223,40 +217,78 @@ __global__ void k_gid(const uint32_t* __restrict__ order, uint32_t n, const unsi
         gid[r] = owner(voff, k, order[r]);
 }
 
-// m = number of distinct edges (last value of the first-of-run scan).
-__global__ void k_set_m(const uint32_t* first_scan, uint64_t m_in, GraphMeta* meta) {
-    meta->m = m_in ? first_scan[m_in - 1] : 0;
-}
+// One pass over the sorted keys (duplicates in place, sentinels last).  A distinct edge is the first
+// key of its run of equal keys.  upper[i] = its upper id, or (duplicates and sentinels) a value above
+// every id (bit nb set, or all ones when ids take 32 bits) so it sorts last.  Its lower id gets one
+// degree: a wavefront walks a chunk of kRunChunk consecutive keys 64 at a time; equal lower ids are
+// contiguous lanes (groups, found by ballot), the last lane of each group adds the group's distinct
+// edges, and the group reaching the wavefront's last lane carries over to the next step, so a long
+// run (a hub's row) costs one atomic per chunk (the sentinel's lower bits match no valid lower id,
+// which is below n - 1).  m = the number of distinct edges, one atomic per workgroup.
+constexpr uint32_t kRunChunk = 64 * 32;
 
-// Upper endpoints of the distinct edges (sorted keys, duplicates in place);
-// duplicates and sentinels get a value above every id (bit nb set, or all
-// ones when ids take 32 bits) so they sort last.
-__global__ void k_upper(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
-                        unsigned long long sentinel, uint32_t* __restrict__ upper) {
+__global__ void k_runs(const unsigned long long* __restrict__ keys, uint32_t nb, uint64_t cap,
+                       unsigned long long sentinel, uint32_t* __restrict__ upper, uint32_t* __restrict__ deg,
+                       GraphMeta* meta) {
     const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
     const uint32_t above = nb >= 32 ? 0xFFFFFFFFu : (1u << nb);
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x)
-        upper[i] = first_of_run(keys, i, sentinel) ? (uint32_t)(keys[i] & mask) : above;
+    const uint32_t lane = threadIdx.x & 63u;
+    __shared__ unsigned long long s_m;
+    if (threadIdx.x == 0) s_m = 0;
+    __syncthreads();
+    unsigned long long firsts = 0;
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    // wavefront-uniform trip counts: every lane takes part in the ballots
+    for (uint64_t c0 = (blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6)) * kRunChunk; c0 < cap;
+         c0 += waves * kRunChunk) {
+        uint32_t clo = 0xFFFFFFFFu, cc = 0;  // carried group (uniform)
+        for (uint32_t st = 0; st < kRunChunk && c0 + st < cap; st += 64) {
+            const uint64_t i = c0 + st + lane;
+            bool first = false;
+            uint32_t lo = 0xFFFFFFFFu;
+            if (i < cap) {
+                const unsigned long long k = keys[i];
+                first = k != sentinel && (i == 0 || keys[i - 1] != k);
+                lo = (uint32_t)(k >> nb);
+                upper[i] = first ? (uint32_t)(k & mask) : above;
+            }
+            const uint32_t lo_prev = (uint32_t)__shfl_up((int)lo, 1, 64);
+            const unsigned long long F = __ballot(first);
+            const unsigned long long H = __ballot(lane == 0 || lo != lo_prev);  // group starts
+            const uint32_t s = 63u - (uint32_t)__builtin_clzll(H & upto);      // this lane's group start
+            const uint32_t c = (uint32_t)__popcll((F & upto) >> s);            // its firsts up to this lane
+            const bool merge = __builtin_amdgcn_readfirstlane(lo) == clo;     // first group continues the carry
+            const uint32_t tail = 63u - (uint32_t)__builtin_clzll(H);          // start of lane 63's group
+            if (lane != 63 && ((H >> (lane + 1)) & 1ull)) {                    // last lane of an inner group
+                const uint32_t cnt = c + ((s == 0 && merge) ? cc : 0u);
+                if (cnt) atomicAdd(&deg[lo], cnt);
+            }
+            const uint32_t c63 = (uint32_t)__builtin_amdgcn_readlane((int)c, 63);
+            const uint32_t lo63 = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
+            if (tail == 0 && merge) {
+                cc += c63;
+            } else {
+                if (!merge && cc && lane == 0) atomicAdd(&deg[clo], cc);
+                clo = lo63;
+                cc = c63;
+            }
+            if (lane == 0) firsts += (unsigned long long)__popcll(F);
+        }
+        if (cc && lane == 0) atomicAdd(&deg[clo], cc);
+    }
+    if (lane == 0 && firsts) atomicAdd(&s_m, firsts);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_m) atomicAdd(&meta->m, s_m);
 }
 
-// Degrees from runs.  Lower endpoints: the sorted keys come in runs of equal
-// lower id; the run's distinct edges are counted with the first-of-run scan
-// (its first element subtracts the scan before it, its last adds the scan at
-// it).  Upper endpoints: the sorted upper ids of the distinct edges, counted
-// by run length (first subtracts its index, last adds index + 1).  Two
-// atomics per run (mod 2^32): no counter is hammered by a hub vertex.
-__global__ void k_degree(const unsigned long long* __restrict__ keys, const uint32_t* __restrict__ first_scan,
-                         const uint32_t* __restrict__ upper, uint32_t nb, uint64_t cap, unsigned long long sentinel,
-                         const GraphMeta* meta, uint32_t* __restrict__ deg) {
+// Upper endpoints' degrees: the sorted upper ids of the distinct edges, counted by run length (the
+// run's first element subtracts its index, its last adds index + 1; two atomics per run, mod 2^32:
+// no counter is hammered by a hub vertex).
+__global__ void k_degree(const uint32_t* __restrict__ upper, uint64_t cap, const GraphMeta* meta,
+                         uint32_t* __restrict__ deg) {
     const uint64_t m = meta->m;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
-        const unsigned long long k = keys[i];
-        if (k != sentinel) {
-            // the sentinel's lower bits exceed every valid lower id, so runs end at it
-            const uint32_t lo = (uint32_t)(k >> nb);
-            if (i == 0 || (uint32_t)(keys[i - 1] >> nb) != lo) atomicSub(&deg[lo], i ? first_scan[i - 1] : 0u);
-            if (i + 1 == cap || (uint32_t)(keys[i + 1] >> nb) != lo) atomicAdd(&deg[lo], first_scan[i]);
-        }
         if (i < m) {
             const uint32_t hi = upper[i];
             if (i == 0 || upper[i - 1] != hi) atomicSub(&deg[hi], (uint32_t)i);
@@ -569,6 +601,12 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
     uint32_t* u32p = nullptr;
     if (sort_keys(nullptr, sz, k64, k64, (size_t)m_in, 0, 2 * nb, 0) == hipSuccess && sz > best) best = sz;
     sz = 0;
+    {
+        auto keys = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
+                                                     CanonKey{u32p, u32p, n, nb, 0ull, nullptr});
+        if (sort_keys(nullptr, sz, keys, k64, (size_t)m_in, 0, 2 * nb, 0) == hipSuccess && sz > best) best = sz;
+    }
+    sz = 0;
     if (sort_keys(nullptr, sz, k64, k64, (size_t)m_in, nb, 2 * nb, 0) == hipSuccess && sz > best) best = sz;
     sz = 0;
     if (sort_keys(nullptr, sz, u32p, u32p, (size_t)m_in, 0, nb < 32 ? nb + 1 : 32, 0) == hipSuccess && sz > best)
@@ -578,11 +616,6 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
                                   (size_t)n, 0, 32) == hipSuccess && sz > best) best = sz;
     sz = 0;
     {
-        auto flags = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
-                                                      FirstOfRun{k64, 0ull});
-        if (rocprim::inclusive_scan(nullptr, sz, flags, u32p, (size_t)m_in, rocprim::plus<uint32_t>()) == hipSuccess &&
-            sz > best) best = sz;
-        sz = 0;
         auto heads = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
                                                       HeadOutDegree{u32p, u32p, nullptr});
         if (rocprim::inclusive_scan(nullptr, sz, heads, k64, (size_t)m_in, rocprim::plus<unsigned long long>()) ==
@@ -682,40 +715,31 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     TC_TRY(fill_u32(t.deg, 0, (size_t)n + 1, stream));
     TC_TRY(fill_u32(t.dplus, 0, (size_t)n + 1, stream));
 
-    // 1-2: canonical keys, sort, unique.
-    if (batch)
+    // 1-2: canonical keys, sort (batches form the keys first: each sample's graph is searched for).
+    tmp = t.sort_tmp_bytes;
+    if (batch) {
         hipLaunchKernelGGL(k_canon_batch, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, src, dst, m_in, n, nb,
                            sentinel, batch->voff, batch->eoff, batch->k, t.keys_a, g.meta);
-    else
-        hipLaunchKernelGGL(k_canon, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, src, dst, m_in, n, nb, sentinel,
-                           t.keys_a, g.meta);
-    TC_TRY(hipGetLastError());
-    tmp = t.sort_tmp_bytes;
-    TC_TRY(sort_keys(t.sort_tmp, tmp, t.keys_a, t.keys_b, (size_t)m_in, 0, 2 * nb, stream));
-    // Distinct edges are numbered by a scan of first-of-run flags (duplicates stay in place).
-    uint32_t* first_scan = reinterpret_cast<uint32_t*>(t.keys_a);
-    {
-        auto flags = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
-                                                      FirstOfRun{t.keys_b, sentinel});
-        tmp = t.sort_tmp_bytes;
-        TC_TRY(rocprim::inclusive_scan(t.sort_tmp, tmp, flags, first_scan, (size_t)m_in, rocprim::plus<uint32_t>(),
-                                       stream));
+        TC_TRY(hipGetLastError());
+        TC_TRY(sort_keys(t.sort_tmp, tmp, t.keys_a, t.keys_b, (size_t)m_in, 0, 2 * nb, stream));
+    } else {
+        auto keys = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
+                                                     CanonKey{src, dst, n, nb, sentinel, g.meta});
+        TC_TRY(sort_keys(t.sort_tmp, tmp, keys, t.keys_b, (size_t)m_in, 0, 2 * nb, stream));
     }
-    hipLaunchKernelGGL(k_set_m, dim3(1), dim3(1), 0, stream, first_scan, m_in, g.meta);
-    TC_TRY(hipGetLastError());
 
-    // 3: degree (from runs of the lower and of the sorted upper endpoints), rank in (degree, id)
-    // order (stable sort keeps ids ascending among equal degrees).
+    // 3: distinct edges and degree (lower ids in the run pass, upper ids from runs of the sorted upper
+    // endpoints), rank in (degree, id) order (stable sort keeps ids ascending among equal degrees).
     {
         uint32_t* up_a = t.aux;
         uint32_t* up_b = t.aux + m_in;
-        hipLaunchKernelGGL(k_upper, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_b, nb, m_in, sentinel,
-                           up_a);
+        const uint64_t chunks = (m_in + kRunChunk - 1) / kRunChunk;  // one wavefront each (4 per block)
+        hipLaunchKernelGGL(k_runs, dim3(grid_for(chunks * 64)), dim3(kThreads), 0, stream, t.keys_b, nb, m_in, sentinel,
+                           up_a, t.deg, g.meta);
         TC_TRY(hipGetLastError());
         tmp = t.sort_tmp_bytes;
         TC_TRY(sort_keys(t.sort_tmp, tmp, up_a, up_b, (size_t)m_in, 0, nb < 32 ? nb + 1 : 32, stream));
-        hipLaunchKernelGGL(k_degree, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, t.keys_b, first_scan, up_b, nb,
-                           m_in, sentinel, g.meta, t.deg);
+        hipLaunchKernelGGL(k_degree, dim3(grid_for(m_in)), dim3(kThreads), 0, stream, up_b, m_in, g.meta, t.deg);
         TC_TRY(hipGetLastError());
     }
     uint32_t* deg_sorted = reinterpret_cast<uint32_t*>(t.skey_a);

@@ -610,7 +610,9 @@ def main():
         "count_only_teps": info.m / (kernel_ms * 1e-3),
         "build_ms": float(np.mean(build_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(per_vertex, args.workload),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     # the committed counter summaries were taken with the default knobs
+                     "traffic": measured_traffic(per_vertex, args.workload) if not args.flags else None,
                      "traffic_kind": "bytes between the L2 and the memory fabric per launch, from request counters "
                                      "resolved by size (32/64/128-byte reads, 32/64-byte writes); Infinity Cache "
                                      "hits included, so not DRAM bytes",
@@ -619,7 +621,7 @@ def main():
                      "kernel": "tc_count_kernel (after tc_hub_kernel, both inside the events)",
                      "algorithmic_bytes": b_alg,
                      "measured_copy_gbs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
-                     "issue": issue_ceiling(per_vertex, args.workload, kernel_ms),
+                     "issue": issue_ceiling(per_vertex, args.workload, kernel_ms) if not args.flags else None,
                      "kernel_source_sha1": kernel_source_sha1()},
     }
     if ablation:

@@ -39,7 +39,7 @@ SPACE = {
     "wg_waves": [4, 8, 16],
     "slots_per_bucket": [2, 4],
     "load_factor_pct": [25, 35, 50],
-    "light_chunk": [1, 2, 4, 8, 16],
+    "light_chunk": [1, 2, 4, 8, 16, 32],
     "hash_kind": [0, 1],
     "wave_max_dplus": [0, 32, 64, 128],
     "order": [0, 0x40, 0x80],

@@ -68,7 +68,7 @@ class Params:
     slots_per_bucket: int = 4
     load_factor_pct: int = 50
     hash_kind: int = 0
-    light_chunk: int = 8
+    light_chunk: int = 16
     grid_wgs: int = 0
     flags: int = 0
 

@@ -489,12 +489,15 @@ tc_status count_one_shot(tc_context* ctx, uint32_t n, uint64_t m_in, const uint3
 
 // ---------------------------------------------------------------- several built graphs, one launch sequence
 
-// Workspace of a multi-graph count: header | (64 KB in) queue heads | descriptors | per-bin fetch prefixes |
+// Workspace of a multi-graph count: header | (80 KB in) queue heads | descriptors | per-bin fetch prefixes |
 // per-vertex staging | global-memory tables.  The header and the heads sit at fixed offsets (the
 // kernels are given those two addresses; everything else is read from the header); every other
 // region grows with (k, n_total, hub_words), so the sizes of any call within a query's bounds fit
 // the query's answer.
-constexpr size_t kMultiHeads = 65536;  // the heads past the first 64 KB (see the count scratch layout)
+// The workspace is used from its first 64 KB boundary (scratch_base); the heads sit 16 KB past the next
+// one, so never within the first 8 KB of a 2 MB page, and the per-vertex staging on a 64 KB boundary
+// (see the count scratch layout).
+constexpr size_t kMultiHeads = 65536 + 16384;
 struct MultiLayout {
     size_t desc, pre, tv, hub, bytes;
     uint32_t hub_wgs;
@@ -506,11 +509,12 @@ MultiLayout multi_layout(const tc_context* ctx, const tc_params& p, uint32_t k, 
     size_t o = align_up(kMultiHeads + 4 * (size_t)tc::kHeadWords);
     M.desc = o;  o = align_up(o + sizeof(tc::MultiDesc) * (size_t)k);
     M.pre = o;   o = align_up(o + 4 * (size_t)tc::kBins * ((size_t)k + 1));
+    o = (o + kScratchAlign - 1) & ~(kScratchAlign - 1);
     M.tv = o;    o = align_up(o + (pv ? 8 * (size_t)n_total : 0));
     const uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)std::max(1, ctx ? ctx->cu_count : 1);
     M.hub_wgs = std::min<uint32_t>(tc::kHubWgs, std::max<uint32_t>(1, grid));
     M.hub = o;   o = align_up(o + 4 * (size_t)hub_words * M.hub_wgs);
-    M.bytes = o;
+    M.bytes = o + kScratchAlign;  // used from the first 64 KB boundary (scratch_base)
     return M;
 }
 
@@ -1140,7 +1144,7 @@ tc_status count_graphs(tc_context* ctx, uint32_t k, tc_graph* const* graphs, uin
     const size_t hdr_bytes = sizeof(tc::MultiHeader), desc_bytes = sizeof(tc::MultiDesc) * (size_t)k;
     tc_context::Stage* st = nullptr;
     if (tc_status e = staging(ctx, hdr_bytes + desc_bytes, &st)) return e;
-    char* ws = static_cast<char*>(d_ws);
+    char* ws = scratch_base(d_ws);
     char* h = static_cast<char*>(st->host);
     std::memset(h, 0, hdr_bytes);
     tc::MultiHeader* H = reinterpret_cast<tc::MultiHeader*>(h);

@@ -98,8 +98,9 @@ uint32_t degree_bits(uint32_t n, uint64_t m_in) {
 
 constexpr uint32_t kScheduleBits = 27;  // schedule keys: bin (0-5) << 24 | 24-bit reversed work
 
-// Canonical key of sample i, formed as the sort reads it (the key histogram and the first pass each
-// read the sample once); an out-of-range id raises the range error and gives the sentinel.
+// Canonical key of sample i, formed as the sort reads its input (its key histogram reads the samples,
+// its first step stores the keys in its own buffer); an out-of-range id raises the range error and
+// gives the sentinel.
 struct CanonKey {
     const uint32_t* src;
     const uint32_t* dst;

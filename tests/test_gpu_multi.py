@@ -173,6 +173,21 @@ def test_replay_equals_eager_batch_workload(ctx, torch):
     check(graphs, t_eager)
 
 
+def test_count_graphs_unaligned_workspace(ctx, torch):
+    """The workspace is used from its first 64 KB boundary: buffers of exactly the queried size at
+    any offset (filled with garbage first), eager and replayed, give the oracle's counts."""
+    graphs = mixed(seed=3, count=3)
+    hs = build_all(ctx, graphs)
+    need = ctx.count_graphs_bytes(len(hs), sum(h.n for h in hs), max(max(h.m_in for h in hs), 1), per_vertex=True)
+    for off in (256, 4096, 65536 - 256, 65536 + 512):
+        buf = torch.full((need + off,), 0x5A, dtype=torch.uint8, device="cuda:0")
+        ws = buf[off:off + need]
+        for replay in (False, True):
+            say(f"[gpu] tc_count_graphs workspace offset {off} replay={replay}")
+            totals, pvs = ctx.count_graphs(hs, per_vertex=True, workspace=ws, replay=replay)
+            check(graphs, totals, pvs)
+
+
 def test_count_graphs_rejects(ctx, torch):
     from paper_2103_08053_amd import Context, Params, TCError
     g = gg.complete(10)

@@ -160,6 +160,26 @@ def test_bins_are_exercised(torch):
     assert_parity(c, g)
 
 
+@pytest.mark.parametrize("flags", [0, 4], ids=["default", "global_tables"])
+def test_scratch_at_unaligned_offsets(torch, flags):
+    """The library uses a caller's count scratch from its first 64 KB boundary: scratch buffers of
+    exactly the queried size starting at any offset (filled with garbage first) give the oracle's
+    counts, through the LDS bins and through the global-memory tables that live in the scratch."""
+    from paper_2103_08053_amd import Context, Params
+    g = gg.dirty(gg.rmat(13, 16, seed=5), seed=4)
+    r = oracle.count(g.n, g.src, g.dst, per_vertex=True)
+    c = Context(0, Params(flags=flags))
+    graph = c.build(g.src, g.dst, g.n)
+    need = c.scratch_bytes(g.n, graph.m_in)
+    for off in (0, 256, 4096, 65536 - 256, 65536 + 512, 3 * 65536 + 768):
+        buf = torch.full((need + off,), 0xA5, dtype=torch.uint8, device="cuda:0")
+        graph.scratch = buf[off:off + need]
+        say(f"[gpu] scratch offset {off} flags {flags:#x}")
+        tot, pv = graph.count(per_vertex=True)
+        assert tot == r.total, off
+        assert (pv.cpu().numpy().astype(np.uint64) == r.per_vertex).all(), off
+
+
 def test_record_layout_flag(torch):
     """TC_F_RECORDS gives the graph its records unless a relabelling or the counting-sort build is asked
     for; the counts agree either way (the element-wise oracle checks are the forced-path cases)."""

@@ -689,8 +689,10 @@ __device__ __forceinline__ uint32_t group_incl_scan(uint32_t v) {
 // Several light vertices in one wavefront: group g = lane / G (64 / G groups) takes the vertex
 // (ug, list at col[bg, bg + dg)) when `has`, with its table in the g-th part of the wavefront's LDS
 // slice (`region` words each), and walks its own flattened 2-hop index space G lanes at a time
-// (loads of kUnroll steps issued before they are looked up; lookups walk their bucket chain lane by
-// lane, which the lightly loaded tables of small vertices keep short).  The per-vertex fixed work
+// (loads of kUnroll steps issued before they are looked up; each lookup reads its home bucket in
+// straight-line code, and the chain is walked lane by lane only when some lane's home bucket is full
+// without its id, which the lightly loaded tables of small vertices make rare: a loop around every
+// lookup kept the scalar unit 73% busy at Erdos-Renyi 2^25 with the record layout).  The per-vertex fixed work
 // (clears, build, records, reductions, flushes) is shared by the groups instead of paid per vertex.
 template <int S, bool PV, int HK, int G>
 __device__ __forceinline__ void process_packed(const CountArgs& a, uint32_t ug, uint32_t bg, uint32_t dg, bool has,
@@ -766,8 +768,26 @@ __device__ __forceinline__ void process_packed(const CountArgs& a, uint32_t ug, 
         }
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
+            // the home bucket for every lane in straight-line code; the chain walk only when some
+            // lane's home bucket is full without its id (rare in these lightly loaded tables)
+            const uint32_t b = hash_of<HK>(w[j], geo.B);
+            const Bucket<S> v = read_bucket<S>(slots, b);
+            bool hit, cont;
             uint32_t slot;
-            if (act[j] && lookup_chain<S, HK>(slots, w[j], geo.B, &slot)) {
+            bucket_step<S>(v, w[j], b, act[j], &hit, &cont, &slot);
+            if (__builtin_amdgcn_ballot_w64(cont)) {
+                if (cont) {
+                    uint32_t bb = (b + 1) & geo.mask;
+                    for (uint32_t t = 1; t < geo.B; ++t) {
+                        const Bucket<S> u = read_bucket<S>(slots, bb);
+                        bool c2;
+                        bucket_step<S>(u, w[j], bb, true, &hit, &c2, &slot);
+                        if (hit || !c2) break;
+                        bb = (bb + 1) & geo.mask;
+                    }
+                }
+            }
+            if (hit) {
                 ++hits;
                 if constexpr (PV) {
                     atomicAdd(&tslot[slot], 1u);

@@ -129,12 +129,14 @@ struct HeadOutDegree {
     }
 };
 
-// Record layout: d+(v) and p(v) = off[v] + v of rank v packed in one word (d+ high), gathered once per
-// edge.  For edge e (row r, head v: the sorted oriented key r << nb | v) the scan of d+(v) writes
-// p(v) into r's record as a side effect (element e + r + 1 of rec; idempotent if evaluated twice).
+// Record layout: for edge e (row r, head v: the sorted oriented key r << nb | v) the scan reads
+// d+(v) as off32[v + 1] - off32[v] (the two offsets share a line but at a line's end), and writes
+// p(v) = off32[v] + v into r's record as a side effect (element e + r + 1 of rec); the row's first
+// edge also writes the row's header d+(r) (element e + r), in the line its list starts in.
+// Idempotent if evaluated twice.
 struct RecordHead {
     const unsigned long long* okeys;
-    const unsigned long long* packed;
+    const uint32_t* off32;
     uint32_t* rec;
     uint32_t nb;
     unsigned long long mask;
@@ -142,9 +144,11 @@ struct RecordHead {
     __device__ unsigned long long operator()(uint64_t e) const {
         if (e >= meta->m) return 0ull;
         const unsigned long long k = okeys[e];
-        const unsigned long long pk = packed[k & mask];
-        rec[e + (k >> nb) + 1] = (uint32_t)pk;
-        return pk >> 32;
+        const uint32_t r = (uint32_t)(k >> nb), v = (uint32_t)(k & mask);
+        const uint32_t o0 = off32[v], o1 = off32[v + 1];
+        rec[e + r + 1] = o0 + v;
+        if (e == 0 || (uint32_t)(okeys[e - 1] >> nb) != r) rec[e + r] = off32[r + 1] - off32[r];
+        return (unsigned long long)(o1 - o0);
     }
 };
 
@@ -416,7 +420,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         const int64_t b = off[r], e = off[r + 1];
         const uint32_t d = (uint32_t)(e - b);
         const unsigned long long w = d ? wscan[e - 1] - (b ? wscan[b - 1] : 0ull) : 0ull;
-        if (rec) rec[b + r] = d;  // the record's header
+        if (rec && d == 0) rec[b + r] = 0;  // the header of a row without edges (the others: in the W scan)
         uint32_t bin;
         if (d < 2 || w == 0) bin = 5;
         else if (caps.force_hub || d > caps.big_cap) bin = 0;
@@ -566,14 +570,6 @@ __global__ void k_gather(const unsigned long long* __restrict__ tv, const uint32
     }
 }
 
-// Record layout: d+(r) << 32 | p(r) for every rank.
-__global__ void k_pack_records(const int64_t* __restrict__ off, uint32_t n, unsigned long long* __restrict__ packed) {
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
-        const int64_t b = off[r];
-        packed[r] = ((unsigned long long)(off[r + 1] - b) << 32) | (unsigned long long)(b + r);
-    }
-}
-
 #define TC_TRY(expr)                        \
     do {                                    \
         hipError_t e_ = (expr);             \
@@ -623,7 +619,7 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
                 hipSuccess && sz > best) best = sz;
         sz = 0;
         auto rheads = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
-                                                       RecordHead{k64, k64, u32p, 1u, 1ull, nullptr});
+                                                       RecordHead{k64, u32p, u32p, 1u, 1ull, nullptr});
         if (rocprim::inclusive_scan(nullptr, sz, rheads, k64, (size_t)m_in, rocprim::plus<unsigned long long>()) ==
                 hipSuccess && sz > best) best = sz;
         sz = 0;
@@ -795,17 +791,15 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
 
     // 6: bins and largest-work-first order; W(u) from a scan of d+(col[e]).
     unsigned long long* wscan = reinterpret_cast<unsigned long long*>(t.keys_a);
-    // 5c with it: the scan's gather of d+(v) also fetches p(v), which goes into the records (the
-    // sorted oriented keys give each edge's row; no relabelling or counting-sort build here).
+    // 5c with it: the scan's gather of d+(v) reads it from the 32-bit offsets, whose lower one is
+    // p(v) - v, which goes into the records (the sorted oriented keys give each edge's row; no
+    // relabelling or counting-sort build here).  Rows without edges get their header in k_schedule.
     uint32_t* rec = (caps.records && !caps.order && !caps.scatter_csr) ? g.rec : nullptr;
     if (rec) {
-        unsigned long long* packed = reinterpret_cast<unsigned long long*>(t.skey_b);
-        hipLaunchKernelGGL(k_pack_records, dim3(grid_for(n)), dim3(kThreads), 0, stream, g.off, n, packed);
-        TC_TRY(hipGetLastError());
         const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
         auto heads = rocprim::make_transform_iterator(
             rocprim::make_counting_iterator<uint64_t>(0),
-            RecordHead{reinterpret_cast<const unsigned long long*>(t.aux), packed, rec, nb, mask, g.meta});
+            RecordHead{reinterpret_cast<const unsigned long long*>(t.aux), g.off32, rec, nb, mask, g.meta});
         tmp = t.sort_tmp_bytes;
         TC_TRY(rocprim::inclusive_scan(t.sort_tmp, tmp, heads, wscan, (size_t)m_in,
                                        rocprim::plus<unsigned long long>(), stream));

@@ -389,6 +389,17 @@ tc_status occupancy(tc_context* ctx, const tc_params& p, bool pv, bool hub, int*
         HIP_TRY(ctx, tc::count_kernel_info_multi(hub, p.slots_per_bucket, pv, p.hash_kind, threads, lds, &q));
     else
         HIP_TRY(ctx, tc::count_kernel_info(hub, sw != 0, p.slots_per_bucket, pv, p.hash_kind, threads, lds, &q));
+    // The query sets the kernel's dynamic-LDS limit to the size asked about; the large-vertex kernel
+    // keeps the full-LDS limit, which its full-LDS launch needs (the half-LDS launch needs less).
+    if (hub && lds < ctx->big_lds_bytes) {
+        int q2 = 0;
+        if (multi)
+            HIP_TRY(ctx, tc::count_kernel_info_multi(true, p.slots_per_bucket, pv, p.hash_kind, threads,
+                                                     ctx->big_lds_bytes, &q2));
+        else
+            HIP_TRY(ctx, tc::count_kernel_info(true, false, p.slots_per_bucket, pv, p.hash_kind, threads,
+                                               ctx->big_lds_bytes, &q2));
+    }
     if (q < 1) return fail(ctx, TC_E_INVALID, "kernel does not fit: %u threads, %u LDS bytes", threads, lds);
     ctx->occ.push_back({(uint32_t)hub, sw, mu, p.slots_per_bucket, (uint32_t)pv, p.hash_kind, threads, lds, q});
     *per_cu = q;
@@ -636,12 +647,19 @@ tc_status tc_create(int hip_device, const tc_params* p, tc_context** out) {
         if (prop.maxSharedMemoryPerMultiProcessor > 2 * (size_t)static_lds) {
             uint32_t lds = (uint32_t)((prop.maxSharedMemoryPerMultiProcessor / 2 - static_lds) & ~(size_t)15);
             for (int i = 0; i < 16 && lds > 4096; ++i, lds -= 256) {
-                int q = 0;
-                if (tc::count_kernel_info(true, false, 4, true, 0, 64 * tc::kMidWaves, lds, &q) != hipSuccess) break;
-                if (q >= 2) {
+                int per_cu = 0;
+                if (tc::count_kernel_info(true, false, 4, true, 0, 64 * tc::kMidWaves, lds, &per_cu) != hipSuccess)
+                    break;
+                if (per_cu >= 2) {
                     c->mid_lds_bytes = lds;
                     break;
                 }
+            }
+            int full = 0;  // back to the full-LDS limit (the queries above lowered it)
+            if (tc::count_kernel_info(true, false, 4, true, 0, 64 * tc::kMaxWaves, c->big_lds_bytes, &full) !=
+                hipSuccess) {
+                delete c;
+                return TC_E_DEVICE;
             }
         }
         if (static_scratch(hip_device, &c->static_scratch) != hipSuccess) {

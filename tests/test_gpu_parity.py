@@ -193,6 +193,19 @@ def test_record_layout_flag(torch):
         res[flags] = (tot, pv.cpu().numpy())
     for flags in res:
         assert res[flags][0] == res[0][0] and (res[flags][1] == res[0][1]).all(), flags
+    # sizes: the records add 4 (m_in + n + 1) bytes of storage (rounded up to the alignment) and
+    # 8 (m_in + 1) bytes of per-vertex staging; where the flag is ignored it changes nothing
+    n, m_in = g.n, g.m_in
+    base = Context(0, Params())
+    rec = Context(0, Params(flags=0x4000))
+    (s0, t0), (s1, t1) = base.footprint(n, m_in), rec.footprint(n, m_in)
+    assert 4 * (m_in + n + 1) <= s1 - s0 < 4 * (m_in + n + 1) + 512 and t1 == t0
+    for other in (0x40, 0x8):
+        a, b = Context(0, Params(flags=other)), Context(0, Params(flags=other | 0x4000))
+        assert a.footprint(n, m_in) == b.footprint(n, m_in), other
+        assert a.scratch_bytes(n, m_in) == b.scratch_bytes(n, m_in), other
+    c0, c1 = base.scratch_bytes(n, m_in), rec.scratch_bytes(n, m_in)
+    assert abs((c1 - c0) - 8 * (m_in + 1)) < 512
 
 
 def test_half_lds_launch(torch):

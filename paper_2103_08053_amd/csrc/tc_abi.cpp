@@ -235,7 +235,7 @@ uint32_t dplus_bound(uint32_t n, uint64_t m_in) {
 bool records_on(const tc_params& p, uint32_t n, uint64_t m_in) {
     return (p.flags & TC_F_RECORDS) &&
            !(p.flags & (TC_F_ORDER_INDEGREE | TC_F_ORDER_COLLECTIVE | TC_F_SCATTER_CSR)) &&
-           m_in + n + 1 < (1ull << 31);
+           tc::record_words(n, m_in) < (1ull << 31);
 }
 
 Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_in, bool batch = false) {
@@ -249,7 +249,8 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     L.s_rank = o;  o = align_up(o + sizeof(uint32_t) * (size_t)n);
     L.s_items = o; o = align_up(o + sizeof(uint32_t) * (size_t)n);
     L.s_gid = o;   o = align_up(o + (batch ? sizeof(uint32_t) * (size_t)n : 0));
-    L.s_rec = o;   o = align_up(o + (L.records ? sizeof(uint32_t) * ((size_t)m_in + n + 1) : 0));
+    L.s_rec = o;   o = align_up(o + (L.records ? sizeof(uint32_t) * tc::record_words(n, m_in) : 0));
+    L.s_place = o; o = align_up(o + (L.records ? 8 * ((size_t)n + 1) : 0));
     L.storage = o;
 
     o = 0;
@@ -266,6 +267,7 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     L.t_rk_a = o;   o = align_up(o + (relabel ? 8 * (size_t)n : 0));
     L.t_rk_b = o;   o = align_up(o + (relabel ? 8 * (size_t)n : 0));
     L.t_off2 = o;   o = align_up(o + (relabel ? 8 * ((size_t)n + 1) : 0));
+    L.t_place = o;  o = align_up(o + (L.records ? 16 * (tc::place_chunks(n) + 1) : 0));
     L.sort_tmp_bytes = align_up(tc::prep_sort_tmp_bytes(n, m_in));
     L.t_sort = o;   o = align_up(o + L.sort_tmp_bytes);
     L.temp = o;
@@ -276,7 +278,7 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     // against 17.3-17.9 ms anywhere past its first 8 KB, so they go last.
     o = 0;
     // (record layout: the per-vertex counts are kept by record position)
-    L.c_tv = o;     o = align_up(o + 8 * (L.records ? (size_t)m_in + n + 1 : (size_t)n));
+    L.c_tv = o;     o = align_up(o + 8 * (L.records ? tc::record_words(n, m_in) : (size_t)n));
     const uint32_t dmax = dplus_bound(n, m_in);
     L.hub_words = tc::geometry(dmax, p.slots_per_bucket, tc::load_recip(p.load_factor_pct), true).words;
     uint32_t grid = p.grid_wgs ? p.grid_wgs : (uint32_t)std::max(1, ctx ? ctx->cu_count : 1);
@@ -299,6 +301,7 @@ tc::GraphDev graph_ptrs(void* storage, const Layout& L) {
     g.items = reinterpret_cast<uint32_t*>(b + L.s_items);
     g.gid = nullptr;
     g.rec = L.records ? reinterpret_cast<uint32_t*>(b + L.s_rec) : nullptr;
+    g.place = L.records ? reinterpret_cast<uint32_t*>(b + L.s_place) : nullptr;
     return g;
 }
 
@@ -317,6 +320,7 @@ tc::BuildTemp temp_ptrs(void* temp, const Layout& L) {
     t.rk_a = relabel ? reinterpret_cast<unsigned long long*>(b + L.t_rk_a) : nullptr;
     t.rk_b = relabel ? reinterpret_cast<unsigned long long*>(b + L.t_rk_b) : nullptr;
     t.off2 = relabel ? reinterpret_cast<int64_t*>(b + L.t_off2) : nullptr;
+    t.place_sz = L.records ? reinterpret_cast<unsigned long long*>(b + L.t_place) : nullptr;
     t.sort_tmp = b + L.t_sort;
     t.sort_tmp_bytes = L.sort_tmp_bytes;
     return t;
@@ -415,7 +419,10 @@ bool needs_hub_launch(const tc_graph* g) {
 // d_totals has g->k entries.  With `record` false no timing events are recorded (stream capture).
 tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex, void* d_scr,
                      const Layout& L, hipStream_t s, bool record = true, uint32_t shard = 0, uint32_t shards = 1) {
-    const tc_params& p = g->p;
+    // Record layout: the tables hash ids with the multiplicative hash, since line-aligned record
+    // positions share their low bits.
+    tc_params p = g->p;
+    if (g->dev.rec) p.hash_kind = 1;
     const bool pv = d_per_vertex != nullptr;
     char* b = scratch_base(d_scr);
     if (g->empty) {
@@ -441,11 +448,12 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.chunk = p.light_chunk;
     a.wide = tc::wide_list_addressing(g->m_in, (p.flags & TC_F_WIDE_ADDR) != 0) ? 1u : 0u;
     // Record layout: lists are read through the records, and ids (tables, tallies) are record positions.
-    const size_t tv_words = g->dev.rec ? (size_t)g->m_in + g->n + 1 : (size_t)g->n;
+    const size_t tv_words = g->dev.rec ? tc::record_words(g->n, g->m_in) : (size_t)g->n;
     if (g->dev.rec) {
         a.rec = g->dev.rec;
         a.col = g->dev.rec;
-        a.wide = tc::wide_list_addressing(g->m_in + g->n + 1, (p.flags & TC_F_WIDE_ADDR) != 0) ? 1u : 0u;
+        a.place = g->dev.place;
+        a.wide = tc::wide_list_addressing(tv_words, (p.flags & TC_F_WIDE_ADDR) != 0) ? 1u : 0u;
     }
     a.shard = shard;
     a.shards = shards;
@@ -465,7 +473,10 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     if (grid_hub < a.hub_wgs) a.hub_wgs = grid_hub;
     HIP_TRY(ctx, tc::fill_u32(a.heads, 0, tc::kHeadWords, s));
     HIP_TRY(ctx, tc::fill_u32(d_totals, 0, 2 * (size_t)g->k, s));
-    if (pv) HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * tv_words, s));
+    if (pv) {
+        if (g->dev.rec) HIP_TRY(ctx, tc::clear_record_staging(a.tv, g->dev.place, g->n, tv_words, s));
+        else HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * tv_words, s));
+    }
     const bool rec = record && ctx->timing;
     if (rec) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
     if (hub) {
@@ -490,7 +501,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
         ctx->have_count = true;
     }
     if (pv)
-        HIP_TRY(ctx, tc::gather_per_vertex(a.tv, g->dev.rank, g->n, g->dev.rec ? g->dev.off32 : nullptr,
+        HIP_TRY(ctx, tc::gather_per_vertex(a.tv, g->dev.rank, g->n, g->dev.rec ? g->dev.place : nullptr,
                                            reinterpret_cast<unsigned long long*>(d_per_vertex), s));
     return TC_OK;
 }

@@ -543,9 +543,9 @@ __device__ __forceinline__ void list_of(const CountArgs& a, uint32_t w, uint32_t
 
 // Table owner u (a rank) as the lists name it (its record position, or u), and where its own list
 // starts in col.
-__device__ __forceinline__ uint32_t own_id(const CountArgs& a, uint32_t u) { return a.rec ? a.off[u] + u : u; }
+__device__ __forceinline__ uint32_t own_id(const CountArgs& a, uint32_t u) { return a.rec ? a.place[2u * u] : u; }
 __device__ __forceinline__ uint32_t own_start(const CountArgs& a, uint32_t u) {
-    return a.rec ? a.off[u] + u + 1u : a.off[u];
+    return a.rec ? a.place[2u * u] + 1u : a.off[u];
 }
 
 // u's list is col[beg, beg + d) (uniform values).  With `pre` (one wavefront, d <= 64; uniform) the

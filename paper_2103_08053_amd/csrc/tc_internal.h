@@ -181,8 +181,10 @@ struct GraphDev {
     uint32_t* rank;     // [n] input id -> rank
     uint32_t* items;    // [n] scheduled vertices by bin (global table, large LDS, workgroup, wavefront, packed, skipped)
     uint32_t* gid;      // [n] graph index of each rank (batches only, else null)
-    uint32_t* rec;      // [m_in + n + 1] vertex records (record layout only, else null): rank r's record
-                        // at p(r) = off[r] + r holds d+(r), then p(v) of each out-neighbour v
+    uint32_t* rec;      // [record_words(n, m_in)] vertex records (record layout only, else null): rank
+                        // r's record at p(r) holds d+(r), then p(v) of each out-neighbour v
+    uint32_t* place;    // [2 (n + 1)] record layout: {p(r), d+(r)} of every rank r; entry n holds the
+                        // records' extent (words up to the end of the last one)
 };
 
 // Batch description for the build (device arrays of k + 1 offsets).
@@ -205,6 +207,7 @@ struct BuildTemp {
     unsigned long long* rk_a;    // [n]
     unsigned long long* rk_b;    // [n]
     int64_t* off2;               // [n + 1]
+    unsigned long long* place_sz;  // [2 (place_chunks(n) + 1)] record layout: words per chunk, then the chunk bases
     void* sort_tmp;
     size_t sort_tmp_bytes;
 };
@@ -218,12 +221,21 @@ struct BinCaps {
     uint32_t order;  // hash-id order: 0 (degree, id) rank, 1 in-degree, 2 collective degree
 };
 
+// Record placement: records go in rank order, kPlaceChunk ranks at a time from a 32-word (128-byte)
+// line boundary, and a record of at most 32 words that would straddle a line boundary starts at the
+// next one instead (the words skipped are fewer than the record's own), so the extent stays below
+// record_words(n, m_in).
+constexpr uint32_t kPlaceChunk = 64;
+__host__ __device__ inline uint64_t place_chunks(uint32_t n) { return ((uint64_t)n + kPlaceChunk - 1) / kPlaceChunk; }
+__host__ __device__ inline uint64_t record_words(uint32_t n, uint64_t m_in) { return 2 * m_in + n + 32 * (place_chunks(n) + 1); }
+
 struct Layout {
     size_t storage, temp, scratch;
     // storage offsets
-    size_t s_meta, s_off, s_off32, s_col, s_rank, s_items, s_gid, s_rec;
+    size_t s_meta, s_off, s_off32, s_col, s_rank, s_items, s_gid, s_rec, s_place;
     // temp offsets
-    size_t t_keys_a, t_keys_b, t_aux, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_rk_a, t_rk_b, t_off2, t_sort;
+    size_t t_keys_a, t_keys_b, t_aux, t_deg, t_dplus, t_order, t_skey_a, t_skey_b, t_rk_a, t_rk_b, t_off2, t_place,
+        t_sort;
     size_t sort_tmp_bytes;
     bool relabel;  // temp holds the relabelling arrays
     bool records;  // storage holds the record layout, per-vertex scratch is indexed by record position
@@ -299,6 +311,7 @@ struct CountArgs {
     uint32_t wide;                   // col spans 4 GiB or more: 64-bit addressing in the probe
     const uint32_t* rec;             // record layout (col == rec): ids are record positions, tv is indexed
                                      // by them, and vertex w's list is rec[w + 1, w + 1 + rec[w])
+    const uint32_t* place;           // record layout: {p(u), d+(u)} of rank u at place[2u]
 };
 
 // tc_prep.hip
@@ -307,9 +320,13 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
                       const GraphDev& g, const BuildTemp& t, const BinCaps& caps, const BatchIn* batch,
                       hipStream_t stream);
 hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream);
-// out[x] = tv[id(rank[x])] with id(r) = r, or the record position off32[r] + r when off32 is given.
-hipError_t gather_per_vertex(const unsigned long long* tv, const uint32_t* rank, uint32_t n, const uint32_t* off32,
+// out[x] = tv[id(rank[x])] with id(r) = r, or the record position place[2r] when place is given.
+hipError_t gather_per_vertex(const unsigned long long* tv, const uint32_t* rank, uint32_t n, const uint32_t* place,
                              unsigned long long* out, hipStream_t stream);
+// Zeroes the record layout's per-vertex staging up to the records' extent (place[2n]), at most max_words
+// 64-bit words.
+hipError_t clear_record_staging(unsigned long long* tv, const uint32_t* place, uint32_t n, size_t max_words,
+                                hipStream_t stream);
 
 // tc_diag.hip: per-table collision statistics of a built graph (the cost model of Equation 2) for
 // the tables the count kernels build; avail[bin] = table words of bins 0-4.  stats = {phi,

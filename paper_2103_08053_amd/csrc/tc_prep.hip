@@ -17,8 +17,10 @@
 //     (the reordering idea of Section 4.1; other orders are optional);
 //  5. CSR: stable radix sort of the oriented keys by row, row lengths from key
 //     runs, scan (int64 offsets);
-//  5c (optional): the record layout: rank r's record at p(r) = off[r] + r holds d+(r) and then
-//     p(v) for each out-neighbour v (written during the scan of step 6, which gathers d+(v) anyway);
+//  5c (optional): the record layout: rank r's record at p(r) holds d+(r) and then p(v) for each
+//     out-neighbour v; records go in rank order, a short one moved to the next 128-byte line where
+//     it would straddle one (placed first, written during the scan of step 6, which gathers d+(v)
+//     anyway);
 //  6. scheduling (Section 4.3): out-degree d+ and collective work
 //     W(u) = sum of d+(v) over out-neighbours v (the collective degree of
 //     Equation 2); vertices with d+ < 2 or W = 0 are skipped, the rest go by
@@ -129,14 +131,15 @@ struct HeadOutDegree {
     }
 };
 
-// Record layout: for edge e (row r, head v: the sorted oriented key r << nb | v) the scan reads
-// d+(v) as off32[v + 1] - off32[v] (the two offsets share a line but at a line's end), and writes
-// p(v) = off32[v] + v into r's record as a side effect (element e + r + 1 of rec); the row's first
-// edge also writes the row's header d+(r) (element e + r), in the line its list starts in.
-// Idempotent if evaluated twice.
+// Record layout: for edge e (row r, head v: the sorted oriented key r << nb | v) the scan reads d+(v)
+// from v's placement {p(v), d+(v)} (one 8-byte load), and writes p(v) into r's record as a side
+// effect (element e - off32[r] of the list behind r's header); the row's first edge also writes the
+// row's header d+(r).  Row r's own placement and offset are read in row order.  Idempotent if
+// evaluated twice.
 struct RecordHead {
     const unsigned long long* okeys;
     const uint32_t* off32;
+    const uint2* place;
     uint32_t* rec;
     uint32_t nb;
     unsigned long long mask;
@@ -145,12 +148,61 @@ struct RecordHead {
         if (e >= meta->m) return 0ull;
         const unsigned long long k = okeys[e];
         const uint32_t r = (uint32_t)(k >> nb), v = (uint32_t)(k & mask);
-        const uint32_t o0 = off32[v], o1 = off32[v + 1];
-        rec[e + r + 1] = o0 + v;
-        if (e == 0 || (uint32_t)(okeys[e - 1] >> nb) != r) rec[e + r] = off32[r + 1] - off32[r];
-        return (unsigned long long)(o1 - o0);
+        const uint2 pv = place[v], pr = place[r];
+        const uint32_t i = (uint32_t)e - off32[r];
+        rec[pr.x + 1u + i] = pv.x;
+        if (i == 0) rec[pr.x] = pr.y;
+        return (unsigned long long)pv.y;
     }
 };
+
+// Record placement (kPlaceChunk ranks per thread, in rank order): the start of a record of s words
+// at cursor c, moved to the next 32-word line boundary when s <= 32 and the record would straddle one.
+__device__ __forceinline__ uint32_t place_at(uint32_t c, uint32_t s) {
+    return (s <= 32u && (c & 31u) + s > 32u) ? ((c + 31u) & ~31u) : c;
+}
+
+// Words of each chunk of records, rounded up to a line (chunks start on line boundaries); entry
+// `chunks` is 0, so that an exclusive scan gives the chunk bases and, last, the extent.
+__global__ void k_place_size(const uint32_t* __restrict__ off32, uint32_t n, unsigned long long* __restrict__ csz) {
+    const uint32_t chunks = (uint32_t)place_chunks(n);
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c <= chunks; c += gridDim.x * blockDim.x) {
+        if (c == chunks) { csz[c] = 0; continue; }
+        const uint32_t r0 = c * kPlaceChunk, r1 = r0 + kPlaceChunk < n ? r0 + kPlaceChunk : n;
+        uint32_t cur = 0;
+        for (uint32_t r = r0; r < r1; ++r) {
+            const uint32_t sz = off32[r + 1] - off32[r] + 1u;
+            cur = place_at(cur, sz) + sz;
+        }
+        csz[c] = (cur + 31u) & ~31u;
+    }
+}
+
+// {p(r), d+(r)} of every rank from the chunk bases; entry n gets {extent, 0}.
+__global__ void k_place_write(const uint32_t* __restrict__ off32, uint32_t n,
+                              const unsigned long long* __restrict__ cbase, uint2* __restrict__ place) {
+    const uint32_t chunks = (uint32_t)place_chunks(n);
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c <= chunks; c += gridDim.x * blockDim.x) {
+        if (c == chunks) { place[n] = make_uint2((uint32_t)cbase[chunks], 0u); continue; }
+        const uint32_t r0 = c * kPlaceChunk, r1 = r0 + kPlaceChunk < n ? r0 + kPlaceChunk : n;
+        uint32_t cur = (uint32_t)cbase[c];
+        for (uint32_t r = r0; r < r1; ++r) {
+            const uint32_t d = off32[r + 1] - off32[r];
+            cur = place_at(cur, d + 1u);
+            place[r] = make_uint2(cur, d);
+            cur += d + 1u;
+        }
+    }
+}
+
+// Zeroes 64-bit words [0, min(2 place[2n], max_words)) (the record layout's per-vertex staging).
+__global__ void k_clear_to_extent(unsigned long long* __restrict__ tv, const uint32_t* __restrict__ place, uint32_t n,
+                                  uint64_t max_words) {
+    const uint64_t ext = place[2 * (uint64_t)n];
+    const uint64_t w = ext < max_words ? ext : max_words;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < w; i += (uint64_t)gridDim.x * blockDim.x)
+        tv[i] = 0ull;
+}
 
 __device__ __forceinline__ bool first_of_run(const unsigned long long* keys, uint64_t i, unsigned long long sentinel) {
     const unsigned long long k = keys[i];
@@ -399,7 +451,8 @@ __global__ void k_pack_census(const int64_t* __restrict__ off, const unsigned lo
 // the vertices whose tables need more than half a CU's LDS (counted by one workgroup per CU), then
 // those up to caps.mid_cap (two workgroups per CU); the work field there takes 23 bits.
 __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long long* __restrict__ wscan, uint32_t n,
-                           BinCaps caps, GraphMeta* meta, uint32_t* __restrict__ skey, uint32_t* __restrict__ rec) {
+                           BinCaps caps, GraphMeta* meta, uint32_t* __restrict__ skey, uint32_t* __restrict__ rec,
+                           const uint32_t* __restrict__ place) {
     __shared__ unsigned long long s_w;
     __shared__ unsigned int s_max, s_bins[6], s_full;
     __shared__ unsigned long long s_bw[6];
@@ -420,7 +473,7 @@ __global__ void k_schedule(const int64_t* __restrict__ off, const unsigned long 
         const int64_t b = off[r], e = off[r + 1];
         const uint32_t d = (uint32_t)(e - b);
         const unsigned long long w = d ? wscan[e - 1] - (b ? wscan[b - 1] : 0ull) : 0ull;
-        if (rec && d == 0) rec[b + r] = 0;  // the header of a row without edges (the others: in the W scan)
+        if (rec && d == 0) rec[place[2 * r]] = 0;  // the header of a row without edges (the others: in the W scan)
         uint32_t bin;
         if (d < 2 || w == 0) bin = 5;
         else if (caps.force_hub || d > caps.big_cap) bin = 0;
@@ -563,10 +616,10 @@ __global__ void k_scatter_u32(const uint32_t* __restrict__ in, const uint32_t* _
 }
 
 __global__ void k_gather(const unsigned long long* __restrict__ tv, const uint32_t* __restrict__ rank, uint32_t n,
-                         const uint32_t* __restrict__ off32, unsigned long long* __restrict__ out) {
+                         const uint32_t* __restrict__ place, unsigned long long* __restrict__ out) {
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
         const uint32_t r = rank[x];
-        out[x] = tv[off32 ? (uint64_t)off32[r] + r : (uint64_t)r];
+        out[x] = tv[place ? place[2 * (uint64_t)r] : r];
     }
 }
 
@@ -584,10 +637,18 @@ hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t gather_per_vertex(const unsigned long long* tv, const uint32_t* rank, uint32_t n, const uint32_t* off32,
+hipError_t gather_per_vertex(const unsigned long long* tv, const uint32_t* rank, uint32_t n, const uint32_t* place,
                              unsigned long long* out, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, stream, tv, rank, n, off32, out);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, stream, tv, rank, n, place, out);
+    return hipGetLastError();
+}
+
+hipError_t clear_record_staging(unsigned long long* tv, const uint32_t* place, uint32_t n, size_t max_words,
+                                hipStream_t stream) {
+    if (max_words == 0) return hipSuccess;
+    const uint32_t grid = std::min<uint32_t>(grid_for(max_words), 16384u);
+    hipLaunchKernelGGL(k_clear_to_extent, dim3(grid), dim3(kThreads), 0, stream, tv, place, n, (uint64_t)max_words);
     return hipGetLastError();
 }
 
@@ -618,8 +679,11 @@ size_t prep_sort_tmp_bytes(uint32_t n, uint64_t m_in) {
         if (rocprim::inclusive_scan(nullptr, sz, heads, k64, (size_t)m_in, rocprim::plus<unsigned long long>()) ==
                 hipSuccess && sz > best) best = sz;
         sz = 0;
+        if (rocprim::exclusive_scan(nullptr, sz, k64, k64, (unsigned long long)0, (size_t)place_chunks(n) + 1,
+                                    rocprim::plus<unsigned long long>()) == hipSuccess && sz > best) best = sz;
+        sz = 0;
         auto rheads = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint64_t>(0),
-                                                       RecordHead{k64, u32p, u32p, 1u, 1ull, nullptr});
+                                                       RecordHead{k64, u32p, nullptr, u32p, 1u, 1ull, nullptr});
         if (rocprim::inclusive_scan(nullptr, sz, rheads, k64, (size_t)m_in, rocprim::plus<unsigned long long>()) ==
                 hipSuccess && sz > best) best = sz;
         sz = 0;
@@ -791,15 +855,28 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
 
     // 6: bins and largest-work-first order; W(u) from a scan of d+(col[e]).
     unsigned long long* wscan = reinterpret_cast<unsigned long long*>(t.keys_a);
-    // 5c with it: the scan's gather of d+(v) reads it from the 32-bit offsets, whose lower one is
-    // p(v) - v, which goes into the records (the sorted oriented keys give each edge's row; no
-    // relabelling or counting-sort build here).  Rows without edges get their header in k_schedule.
+    // 5c with it: records are placed first ({p(r), d+(r)} per rank), then the scan's gather of d+(v)
+    // reads v's placement, whose p(v) goes into the records (the sorted oriented keys give each edge's
+    // row; no relabelling or counting-sort build here).  Rows without edges get their header in
+    // k_schedule.
     uint32_t* rec = (caps.records && !caps.order && !caps.scatter_csr) ? g.rec : nullptr;
     if (rec) {
+        const uint64_t chunks = place_chunks(n);
+        hipLaunchKernelGGL(k_place_size, dim3(grid_for(chunks + 1)), dim3(kThreads), 0, stream, g.off32, n,
+                           t.place_sz);
+        TC_TRY(hipGetLastError());
+        tmp = t.sort_tmp_bytes;
+        unsigned long long* cbase = t.place_sz + chunks + 1;
+        TC_TRY(rocprim::exclusive_scan(t.sort_tmp, tmp, t.place_sz, cbase, (unsigned long long)0,
+                                       (size_t)chunks + 1, rocprim::plus<unsigned long long>(), stream));
+        uint2* place = reinterpret_cast<uint2*>(g.place);
+        hipLaunchKernelGGL(k_place_write, dim3(grid_for(chunks + 1)), dim3(kThreads), 0, stream, g.off32, n,
+                           cbase, place);
+        TC_TRY(hipGetLastError());
         const unsigned long long mask = (nb >= 32) ? 0xFFFFFFFFull : ((1ull << nb) - 1);
         auto heads = rocprim::make_transform_iterator(
             rocprim::make_counting_iterator<uint64_t>(0),
-            RecordHead{reinterpret_cast<const unsigned long long*>(t.aux), g.off32, rec, nb, mask, g.meta});
+            RecordHead{reinterpret_cast<const unsigned long long*>(t.aux), g.off32, place, rec, nb, mask, g.meta});
         tmp = t.sort_tmp_bytes;
         TC_TRY(rocprim::inclusive_scan(t.sort_tmp, tmp, heads, wscan, (size_t)m_in,
                                        rocprim::plus<unsigned long long>(), stream));
@@ -818,7 +895,7 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
     // at most 1024 blocks: each block ends with a few global atomics on the same summary words
     uint32_t* skey = reinterpret_cast<uint32_t*>(t.skey_a);
     hipLaunchKernelGGL(k_schedule, dim3(std::min(grid_for(n), 1024u)), dim3(kThreads), 0, stream, g.off, wscan, n, caps, g.meta,
-                       skey, rec);
+                       skey, rec, rec ? g.place : nullptr);
     TC_TRY(hipGetLastError());
     tmp = t.sort_tmp_bytes;
     TC_TRY(sort_pairs(t.sort_tmp, tmp, skey, reinterpret_cast<uint32_t*>(t.skey_b), g.items, (size_t)n, kScheduleBits,

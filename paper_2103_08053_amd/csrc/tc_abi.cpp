@@ -474,7 +474,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     HIP_TRY(ctx, tc::fill_u32(a.heads, 0, tc::kHeadWords, s));
     HIP_TRY(ctx, tc::fill_u32(d_totals, 0, 2 * (size_t)g->k, s));
     if (pv) {
-        if (g->dev.rec) HIP_TRY(ctx, tc::clear_record_staging(a.tv, g->dev.place, g->n, tv_words, s));
+        if (g->dev.rec) HIP_TRY(ctx, tc::clear_record_staging(a.tv, g->dev.place, g->n, s));
         else HIP_TRY(ctx, tc::fill_u32(a.tv, 0, 2 * tv_words, s));
     }
     const bool rec = record && ctx->timing;

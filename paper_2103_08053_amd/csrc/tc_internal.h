@@ -323,10 +323,9 @@ hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream);
 // out[x] = tv[id(rank[x])] with id(r) = r, or the record position place[2r] when place is given.
 hipError_t gather_per_vertex(const unsigned long long* tv, const uint32_t* rank, uint32_t n, const uint32_t* place,
                              unsigned long long* out, hipStream_t stream);
-// Zeroes the record layout's per-vertex staging up to the records' extent (place[2n]), at most max_words
-// 64-bit words.
-hipError_t clear_record_staging(unsigned long long* tv, const uint32_t* place, uint32_t n, size_t max_words,
-                                hipStream_t stream);
+// Zeroes the record layout's per-vertex staging at every record's start (place[2r], r < n): the only
+// entries a count adds to.
+hipError_t clear_record_staging(unsigned long long* tv, const uint32_t* place, uint32_t n, hipStream_t stream);
 
 // tc_diag.hip: per-table collision statistics of a built graph (the cost model of Equation 2) for
 // the tables the count kernels build; avail[bin] = table words of bins 0-4.  stats = {phi,

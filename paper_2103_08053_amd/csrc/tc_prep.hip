@@ -195,13 +195,12 @@ __global__ void k_place_write(const uint32_t* __restrict__ off32, uint32_t n,
     }
 }
 
-// Zeroes 64-bit words [0, min(2 place[2n], max_words)) (the record layout's per-vertex staging).
-__global__ void k_clear_to_extent(unsigned long long* __restrict__ tv, const uint32_t* __restrict__ place, uint32_t n,
-                                  uint64_t max_words) {
-    const uint64_t ext = place[2 * (uint64_t)n];
-    const uint64_t w = ext < max_words ? ext : max_words;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < w; i += (uint64_t)gridDim.x * blockDim.x)
-        tv[i] = 0ull;
+// Zeroes the record layout's per-vertex staging where the count adds to it: at every record's start
+// (the ids the count handles are record positions), in rank order.
+__global__ void k_clear_record_starts(unsigned long long* __restrict__ tv, const uint32_t* __restrict__ place,
+                                      uint32_t n) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        tv[place[2 * (uint64_t)r]] = 0ull;
 }
 
 __device__ __forceinline__ bool first_of_run(const unsigned long long* keys, uint64_t i, unsigned long long sentinel) {
@@ -644,11 +643,9 @@ hipError_t gather_per_vertex(const unsigned long long* tv, const uint32_t* rank,
     return hipGetLastError();
 }
 
-hipError_t clear_record_staging(unsigned long long* tv, const uint32_t* place, uint32_t n, size_t max_words,
-                                hipStream_t stream) {
-    if (max_words == 0) return hipSuccess;
-    const uint32_t grid = std::min<uint32_t>(grid_for(max_words), 16384u);
-    hipLaunchKernelGGL(k_clear_to_extent, dim3(grid), dim3(kThreads), 0, stream, tv, place, n, (uint64_t)max_words);
+hipError_t clear_record_staging(unsigned long long* tv, const uint32_t* place, uint32_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_record_starts, dim3(grid_for(n)), dim3(kThreads), 0, stream, tv, place, n);
     return hipGetLastError();
 }
 

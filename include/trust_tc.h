@@ -61,8 +61,8 @@ typedef struct tc_params {
                                    (capped by what fits in wg_lds_bytes / wg_waves); 0 = largest that fits */
     uint32_t slots_per_bucket;  /* S: 1, 2 or 4 slots per hash bucket */
     uint32_t load_factor_pct;   /* buckets B = smallest power of two with B*S*load >= d+, and B >= d+; 10..100 */
-    uint32_t hash_kind;         /* 0: low bits of the degree rank; 1: multiplicative (Fibonacci) hash
-                                   (always 1 for graphs built with the record layout, TC_F_RECORDS) */
+    uint32_t hash_kind;         /* 0: low bits of the id (the degree rank, or the record id with
+                                   TC_F_RECORDS); 1: multiplicative (Fibonacci) hash */
     uint32_t light_chunk;       /* vertices a wavefront takes per queue access, 1..256 */
     uint32_t grid_wgs;          /* persistent grid size in workgroups; 0 = fill the device */
     uint32_t flags;             /* TC_F_* below */
@@ -98,8 +98,9 @@ typedef struct tc_params {
                                     counts read lists through it: a 2-hop list starts in the line of its
                                     length instead of behind a separate offset load, and a record of at
                                     most 32 words that would straddle a 128-byte line starts at the next
-                                    one (so record positions share low bits, and the count's tables take
-                                    the multiplicative hash whatever hash_kind says).  Not with the
+                                    one (lists name records by position with its low 5 bits XORed with
+                                    those of its line index, so that hashing by low bits still spreads
+                                    them).  Not with the
                                     TC_F_ORDER_* relabellings or TC_F_SCATTER_CSR (ignored there), nor
                                     where R = 2 m_in + n + 32 (ceil(n / 64) + 1) reaches 2^31; the
                                     graph's storage grows by 4 R + 8 (n + 1) bytes, the build's

@@ -277,7 +277,7 @@ Layout layout(const tc_context* ctx, const tc_params& p, uint32_t n, uint64_t m_
     // separately allocated scratch begins) the per-vertex count at R-MAT scale 22 measured 18.8 ms
     // against 17.3-17.9 ms anywhere past its first 8 KB, so they go last.
     o = 0;
-    // (record layout: the per-vertex counts are kept by record position)
+    // (record layout: the per-vertex counts are kept by record id)
     L.c_tv = o;     o = align_up(o + 8 * (L.records ? tc::record_words(n, m_in) : (size_t)n));
     const uint32_t dmax = dplus_bound(n, m_in);
     L.hub_words = tc::geometry(dmax, p.slots_per_bucket, tc::load_recip(p.load_factor_pct), true).words;
@@ -419,10 +419,7 @@ bool needs_hub_launch(const tc_graph* g) {
 // d_totals has g->k entries.  With `record` false no timing events are recorded (stream capture).
 tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uint64_t* d_per_vertex, void* d_scr,
                      const Layout& L, hipStream_t s, bool record = true, uint32_t shard = 0, uint32_t shards = 1) {
-    // Record layout: the tables hash ids with the multiplicative hash, since line-aligned record
-    // positions share their low bits.
-    tc_params p = g->p;
-    if (g->dev.rec) p.hash_kind = 1;
+    const tc_params& p = g->p;
     const bool pv = d_per_vertex != nullptr;
     char* b = scratch_base(d_scr);
     if (g->empty) {
@@ -447,7 +444,7 @@ tc_status count_into(tc_context* ctx, const tc_graph* g, uint64_t* d_totals, uin
     a.lrecip = tc::load_recip(p.load_factor_pct);
     a.chunk = p.light_chunk;
     a.wide = tc::wide_list_addressing(g->m_in, (p.flags & TC_F_WIDE_ADDR) != 0) ? 1u : 0u;
-    // Record layout: lists are read through the records, and ids (tables, tallies) are record positions.
+    // Record layout: lists are read through the records, and ids (tables, tallies) are record ids.
     const size_t tv_words = g->dev.rec ? tc::record_words(g->n, g->m_in) : (size_t)g->n;
     if (g->dev.rec) {
         a.rec = g->dev.rec;

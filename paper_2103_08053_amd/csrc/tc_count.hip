@@ -528,22 +528,25 @@ struct NoMid {
     __device__ void operator()() const {}
 };
 
-// 2-hop list of vertex w: col[start, start + len).  Record layout: w is a record position, the length
-// heads the record and the list follows it (one line for both in the common case); otherwise w is a
-// rank and the bounds come from the offsets (a line of their own).
+// 2-hop list of vertex w: col[start, start + len).  Record layout: w is a record id (its position
+// p = rec_id(w)), the length heads the record and the list follows it in the same line; otherwise w
+// is a rank and the bounds come from the offsets (a line of their own).
 __device__ __forceinline__ void list_of(const CountArgs& a, uint32_t w, uint32_t& start, uint32_t& len) {
     if (a.rec) {
-        len = a.rec[w];
-        start = w + 1u;
+        const uint32_t p = rec_id(w);
+        len = a.rec[p];
+        start = p + 1u;
     } else {
         start = a.off[w];
         len = a.off[w + 1] - start;
     }
 }
 
-// Table owner u (a rank) as the lists name it (its record position, or u), and where its own list
+// Table owner u (a rank) as the lists name it (its record id, or u), and where its own list
 // starts in col.
-__device__ __forceinline__ uint32_t own_id(const CountArgs& a, uint32_t u) { return a.rec ? a.place[2u * u] : u; }
+__device__ __forceinline__ uint32_t own_id(const CountArgs& a, uint32_t u) {
+    return a.rec ? rec_id(a.place[2u * u]) : u;
+}
 __device__ __forceinline__ uint32_t own_start(const CountArgs& a, uint32_t u) {
     return a.rec ? a.place[2u * u] + 1u : a.off[u];
 }

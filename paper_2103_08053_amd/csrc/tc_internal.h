@@ -182,7 +182,7 @@ struct GraphDev {
     uint32_t* items;    // [n] scheduled vertices by bin (global table, large LDS, workgroup, wavefront, packed, skipped)
     uint32_t* gid;      // [n] graph index of each rank (batches only, else null)
     uint32_t* rec;      // [record_words(n, m_in)] vertex records (record layout only, else null): rank
-                        // r's record at p(r) holds d+(r), then p(v) of each out-neighbour v
+                        // r's record at p(r) holds d+(r), then rec_id(p(v)) of each out-neighbour v
     uint32_t* place;    // [2 (n + 1)] record layout: {p(r), d+(r)} of every rank r; entry n holds the
                         // records' extent (words up to the end of the last one)
 };
@@ -228,6 +228,10 @@ struct BinCaps {
 constexpr uint32_t kPlaceChunk = 64;
 __host__ __device__ inline uint64_t place_chunks(uint32_t n) { return ((uint64_t)n + kPlaceChunk - 1) / kPlaceChunk; }
 __host__ __device__ inline uint64_t record_words(uint32_t n, uint64_t m_in) { return 2 * m_in + n + 32 * (place_chunks(n) + 1); }
+// Id of the record at position p, and position of the record with id p (the map is its own inverse):
+// the low 5 bits XORed with those of the line index, so that records moved to a line start still
+// spread over hash buckets by their low bits.  Ids stay within p's 32-word line.
+__host__ __device__ inline uint32_t rec_id(uint32_t p) { return p ^ ((p >> 5) & 31u); }
 
 struct Layout {
     size_t storage, temp, scratch;
@@ -238,7 +242,7 @@ struct Layout {
         t_sort;
     size_t sort_tmp_bytes;
     bool relabel;  // temp holds the relabelling arrays
-    bool records;  // storage holds the record layout, per-vertex scratch is indexed by record position
+    bool records;  // storage holds the record layout, per-vertex scratch is indexed by record id
     // scratch offsets
     size_t c_tv, c_heads, c_total, c_hub;
     uint64_t hub_words;
@@ -309,8 +313,9 @@ struct CountArgs {
     uint32_t subwave;                // 0: virtual combination; 8/16/32/64: lanes per out-neighbour list
     uint32_t shard, shards;          // count only table owners u (rank) with u % shards == shard
     uint32_t wide;                   // col spans 4 GiB or more: 64-bit addressing in the probe
-    const uint32_t* rec;             // record layout (col == rec): ids are record positions, tv is indexed
-                                     // by them, and vertex w's list is rec[w + 1, w + 1 + rec[w])
+    const uint32_t* rec;             // record layout (col == rec): ids are record ids (rec_id of the
+                                     // position), tv is indexed by them, and with p = rec_id(w) vertex
+                                     // w's list is rec[p + 1, p + 1 + rec[p])
     const uint32_t* place;           // record layout: {p(u), d+(u)} of rank u at place[2u]
 };
 
@@ -320,7 +325,7 @@ hipError_t prep_build(uint32_t n, uint64_t m_in, const uint32_t* src, const uint
                       const GraphDev& g, const BuildTemp& t, const BinCaps& caps, const BatchIn* batch,
                       hipStream_t stream);
 hipError_t fill_u32(void* p, uint32_t value, size_t words, hipStream_t stream);
-// out[x] = tv[id(rank[x])] with id(r) = r, or the record position place[2r] when place is given.
+// out[x] = tv[id(rank[x])] with id(r) = r, or the record id rec_id(place[2r]) when place is given.
 hipError_t gather_per_vertex(const unsigned long long* tv, const uint32_t* rank, uint32_t n, const uint32_t* place,
                              unsigned long long* out, hipStream_t stream);
 // Zeroes the record layout's per-vertex staging at every record's start (place[2r], r < n): the only

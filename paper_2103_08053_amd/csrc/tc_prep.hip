@@ -132,7 +132,7 @@ struct HeadOutDegree {
 };
 
 // Record layout: for edge e (row r, head v: the sorted oriented key r << nb | v) the scan reads d+(v)
-// from v's placement {p(v), d+(v)} (one 8-byte load), and writes p(v) into r's record as a side
+// from v's placement {p(v), d+(v)} (one 8-byte load), and writes v's record id into r's record as a side
 // effect (element e - off32[r] of the list behind r's header); the row's first edge also writes the
 // row's header d+(r).  Row r's own placement and offset are read in row order.  Idempotent if
 // evaluated twice.
@@ -150,7 +150,7 @@ struct RecordHead {
         const uint32_t r = (uint32_t)(k >> nb), v = (uint32_t)(k & mask);
         const uint2 pv = place[v], pr = place[r];
         const uint32_t i = (uint32_t)e - off32[r];
-        rec[pr.x + 1u + i] = pv.x;
+        rec[pr.x + 1u + i] = rec_id(pv.x);
         if (i == 0) rec[pr.x] = pr.y;
         return (unsigned long long)pv.y;
     }
@@ -196,11 +196,11 @@ __global__ void k_place_write(const uint32_t* __restrict__ off32, uint32_t n,
 }
 
 // Zeroes the record layout's per-vertex staging where the count adds to it: at every record's start
-// (the ids the count handles are record positions), in rank order.
+// (the ids the count handles are record ids), in rank order.
 __global__ void k_clear_record_starts(unsigned long long* __restrict__ tv, const uint32_t* __restrict__ place,
                                       uint32_t n) {
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
-        tv[place[2 * (uint64_t)r]] = 0ull;
+        tv[rec_id(place[2 * (uint64_t)r])] = 0ull;
 }
 
 __device__ __forceinline__ bool first_of_run(const unsigned long long* keys, uint64_t i, unsigned long long sentinel) {
@@ -618,7 +618,7 @@ __global__ void k_gather(const unsigned long long* __restrict__ tv, const uint32
                          const uint32_t* __restrict__ place, unsigned long long* __restrict__ out) {
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
         const uint32_t r = rank[x];
-        out[x] = tv[place ? place[2 * (uint64_t)r] : r];
+        out[x] = tv[place ? rec_id(place[2 * (uint64_t)r]) : r];
     }
 }
 

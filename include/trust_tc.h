@@ -94,15 +94,15 @@ typedef struct tc_params {
                                     CU); default: those whose tables fit half a CU's LDS are counted by a
                                     second launch with two workgroups per CU */
 #define TC_F_RECORDS     0x4000u /* the build also lays each vertex's out-degree and out-list out as one
-                                    record (d+, then the neighbours' record positions), and single-graph
+                                    record (d+, then the neighbours' records' ids), and single-graph
                                     counts read lists through it: a 2-hop list starts in the line of its
                                     length instead of behind a separate offset load, and a record of at
                                     most 32 words that would straddle a 128-byte line starts at the next
                                     one (lists name records by position with its low 5 bits XORed with
                                     those of its line index, so that hashing by low bits still spreads
-                                    them).  Not with the
-                                    TC_F_ORDER_* relabellings or TC_F_SCATTER_CSR (ignored there), nor
-                                    where R = 2 m_in + n + 32 (ceil(n / 64) + 1) reaches 2^31; the
+                                    them).  Not with the TC_F_ORDER_* relabellings or TC_F_SCATTER_CSR
+                                    (ignored there), nor where R = 2 m_in + n + 32 (ceil(n / 64) + 1)
+                                    reaches 2^31; the
                                     graph's storage grows by 4 R + 8 (n + 1) bytes, the build's
                                     temporaries by 16 (ceil(n / 64) + 1) and a per-vertex count's
                                     scratch by 8 (R - n) bytes */

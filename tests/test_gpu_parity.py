@@ -213,6 +213,20 @@ def test_record_layout_flag(torch):
     assert abs((c1 - c0) - 8 * (words - n)) < 512
 
 
+def test_record_placement_near_line_size(torch):
+    """Record layout where records are about a 128-byte line long (mean out-degree near 32, so many
+    records of up to 32 words would straddle a line and are moved to the next one, and the longer
+    ones are not), with vertex counts that leave a partial chunk of 64 ranks, and a near-complete
+    graph whose records take every length from 1 to 65 words: every count equals the oracle's."""
+    from paper_2103_08053_amd import Context, Params
+    c = Context(0, Params(flags=0x4000))
+    graphs = [gg.erdos_renyi(n, n * deg // 2, seed=seed) for n, deg, seed in ((64 * 37 + 7, 64, 1), (1000, 70, 2))]
+    for g in graphs + [gg.complete(65)]:
+        graph = c.build(g.src, g.dst, g.n)
+        assert graph.info().records == 1
+        assert_parity(c, g)
+
+
 def test_half_lds_launch(torch):
     """Large-LDS-bin vertices in both launches: K_2500 has out-degrees 0..2499 in rank order, so
     those above the half-LDS limit (about 2000) take the full-LDS launch and those between the

@@ -17,10 +17,10 @@
 //     (the reordering idea of Section 4.1; other orders are optional);
 //  5. CSR: stable radix sort of the oriented keys by row, row lengths from key
 //     runs, scan (int64 offsets);
-//  5c (optional): the record layout: rank r's record at p(r) holds d+(r) and then p(v) for each
-//     out-neighbour v; records go in rank order, a short one moved to the next 128-byte line where
-//     it would straddle one (placed first, written during the scan of step 6, which gathers d+(v)
-//     anyway);
+//  5c (optional): the record layout: rank r's record at p(r) holds d+(r) and then the record id
+//     rec_id(p(v)) of each out-neighbour v; records go in rank order, a short one moved to the next
+//     128-byte line where it would straddle one (placed first, written during the scan of step 6,
+//     which gathers d+(v) anyway);
 //  6. scheduling (Section 4.3): out-degree d+ and collective work
 //     W(u) = sum of d+(v) over out-neighbours v (the collective degree of
 //     Equation 2); vertices with d+ < 2 or W = 0 are skipped, the rest go by
